@@ -1,0 +1,199 @@
+/*
+ * so2dr.h -- C interface of the out-of-core stencil library for MI355X.
+ *
+ * The library runs a time-stepped 2D/3D stencil sweep (paper Sec. II-A) on a
+ * grid that lives in pinned host memory and may be far larger than the device
+ * memory the caller grants it.  The grid is cut into chunks along its slowest
+ * axis and streamed host -> HBM -> host (Sec. II-A, Fig. 1b).  Following
+ * Algorithm 1 and Sec. IV, each chunk advances tb_depth steps per residency;
+ * the round-start planes it shares with the next chunk are handed over in HBM
+ * (the region-sharing buffer, Sec. II-B and Fig. 2) so they cross PCIe once;
+ * and each chunk recomputes its shared overlap itself (Sec. IV-B, Fig. 4) so
+ * its kernels can fuse k_on steps in LDS and registers.  The output of every
+ * run equals the plain in-core Jacobi sweep; a plan with one chunk and
+ * tb_depth = T is that in-core sweep, run by the same executor and kernels.
+ *
+ * Conventions shared by every call:
+ *   - Grid layout: x fastest (contiguous), then y, then z.  A 3D grid is cut
+ *     along z; a 2D grid (nz = 1) is cut along y.  Host arrays hold exactly
+ *     nx*ny*nz elements of the storage type, no padding.
+ *   - Every cell is updated every step; cells outside the grid come from the
+ *     boundary rule of their axis (zero Dirichlet or periodic).  The cut axis
+ *     must be zero Dirichlet.
+ *   - Stencil weights: one double per stencil point, listed in lexicographic
+ *     order of the (dz, dy, dx) offset triples (2D: (dy, dx)).  Star = the
+ *     centre plus the axis points at distance 1..radius (Fig. 1a); box = the
+ *     full (2r+1)^ndim cube (Table III).  Weight w multiplies the value at
+ *     x + offset (a correlation).  Each cell's sum is formed in that same
+ *     lexicographic order with fused multiply-adds, in FP32 for F32/BF16/F16
+ *     storage (weights rounded to FP32) and in FP64 for F64 storage; BF16 and
+ *     F16 results are rounded to nearest-even after every step.  The result of
+ *     a run therefore does not depend on chunk count, tb_depth, k_on or slot
+ *     count: only on the storage type.
+ *   - Return codes: 0 on success, a negative SO2DR_E_* code otherwise; the
+ *     thread-local message from so2dr_last_error() then says why.  No call
+ *     throws or aborts.
+ */
+#ifndef SO2DR_H
+#define SO2DR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SO2DR_OK 0
+#define SO2DR_E_INVALID (-1)     /* malformed descriptor or argument */
+#define SO2DR_E_BUDGET (-2)      /* no plan fits the device budget */
+#define SO2DR_E_UNSUPPORTED (-3) /* stencil / dtype / depth not built */
+#define SO2DR_E_NOT_PINNED (-4)  /* a host array is not pinned (page-locked) memory */
+#define SO2DR_E_HIP (-5)         /* the HIP runtime reported an error */
+#define SO2DR_E_UNBOUND (-6)     /* run before so2dr_plan_bind */
+
+typedef enum { SO2DR_F32 = 0, SO2DR_F64 = 1, SO2DR_BF16 = 2, SO2DR_F16 = 3 } so2dr_dtype;
+typedef enum { SO2DR_STAR = 0, SO2DR_BOX = 1 } so2dr_shape;
+typedef enum { SO2DR_DIRICHLET0 = 0, SO2DR_PERIODIC = 1 } so2dr_bc;
+
+/* Problem and run-time configuration: the variables of the paper's Table I
+ * (dim, sz, r, d, S_tot, S_TB, N_strm, C_dmem) plus the stencil itself. */
+typedef struct {
+  int ndim;                   /* 2 or 3 */
+  int64_t nx, ny, nz;         /* grid extents; nz must be 1 when ndim == 2 */
+  int shape;                  /* so2dr_shape */
+  int radius;                 /* stencil radius r >= 1 */
+  const double *weights;      /* n_weights values, lexicographic (dz,dy,dx); copied */
+  int n_weights;
+  int bc[3];                  /* so2dr_bc for x, y, z; the cut axis must be DIRICHLET0 */
+  int storage;                /* so2dr_dtype of host and HBM fields */
+  int T;                      /* total time steps (S_tot) */
+  int n_chunks;               /* d; 0 = choose the fewest that fit the budget */
+  int tb_depth;               /* K = S_TB: steps per HBM residency; 0 = T */
+  int k_on;                   /* steps fused per kernel launch; 0 = automatic */
+  int n_slots;                /* in-flight chunks (= streams); 0 = automatic, at most 3 */
+  size_t device_budget_bytes; /* hard cap on the device memory the plan may use */
+  int adjoint;                /* 1: also reserve what so2dr_adjoint_run needs */
+} so2dr_desc;
+
+/* What the planner chose (all sizes in bytes unless noted). */
+typedef struct {
+  int64_t n_axis;             /* length of the cut axis (planes) */
+  int64_t plane_elems;        /* elements per plane */
+  int n_chunks, tb_depth, k_on, n_slots, n_rounds;
+  int max_chunk_planes;       /* planes owned by the largest chunk */
+  int slot_planes;            /* planes in one slot buffer */
+  int max_k_on;               /* deepest fused kernel built for this stencil */
+  size_t workspace_bytes;     /* everything the plan uses; <= budget */
+  size_t slot_bytes;          /* one slot = two ping-pong buffers */
+  size_t rs_bytes;            /* region-sharing buffer */
+  size_t scratch_bytes;       /* reduction scratch (adjoint) */
+  double redundant_fraction;  /* recomputed / useful cell updates */
+  int64_t n_ops;              /* entries in the operation schedule */
+} so2dr_plan_info;
+
+/* One entry of the schedule the executor runs (Algorithm 1, unrolled).
+ * Plane ranges are half-open, in global plane indices of the cut axis. */
+typedef enum {
+  SO2DR_OP_H2D = 0,      /* host planes [z0,z1) -> slot buffer buf_out */
+  SO2DR_OP_RS_READ = 1,  /* region-sharing buffer -> slot buffer buf_out planes [z0,z1) */
+  SO2DR_OP_RS_WRITE = 2, /* slot buffer buf_in planes [z0,z1) -> region-sharing buffer */
+  SO2DR_OP_KERNEL = 3,   /* levels steps: buf_in (valid [in_z0,in_z1)) -> buf_out [z0,z1) */
+  SO2DR_OP_D2H = 4       /* slot buffer buf_in planes [z0,z1) -> host planes [z0,z1) */
+} so2dr_op_kind;
+
+typedef struct {
+  int kind;               /* so2dr_op_kind */
+  int round, chunk, slot;
+  int64_t z0, z1;         /* planes written (H2D, RS_READ, KERNEL, D2H) or read (RS_WRITE) */
+  int64_t in_z0, in_z1;   /* KERNEL: valid planes of the input level */
+  int level_in;           /* KERNEL: time level (within the round) of the input */
+  int levels;             /* KERNEL: steps fused in this launch */
+  int buf_in, buf_out;    /* slot buffer index 0/1 (-1 when not used) */
+  int64_t buf_z0;         /* global plane held at index 0 of this chunk's slot buffers */
+} so2dr_op;
+
+/* Per-run measurements.  Times come from HIP events when timing is enabled
+ * (so2dr_plan_set_timing), else they are 0 except wall_ms. */
+typedef struct {
+  double wall_ms;              /* first enqueue to last completion, host clock */
+  double h2d_ms, d2h_ms, d2d_ms, kernel_ms;   /* summed event durations per category */
+  uint64_t bytes_h2d, bytes_d2h, bytes_d2d;
+  uint64_t kernel_launches;
+  uint64_t cell_updates;       /* useful: nx*ny*nz*steps */
+  uint64_t cell_updates_done;  /* including the redundant halo recomputation */
+  uint64_t kernel_alg_bytes;   /* sum over launches of (input area + output area) * elem size */
+  int rounds_done;
+} so2dr_stats;
+
+/* Validate the descriptor and build the plan: chunk bounds, per-round depth
+ * k' (Algorithm 1, rounds of tb_depth steps with the remainder last), the
+ * per-launch fused depths, the shrinking compute areas of Sec. IV-B, slot
+ * and region-sharing sizes, and the device-byte total, which must not exceed
+ * device_budget_bytes.  Host-only: needs no GPU.  *out is owned by the caller
+ * and released with so2dr_plan_destroy.  Errors: E_INVALID, E_BUDGET,
+ * E_UNSUPPORTED. */
+int so2dr_plan_create(const so2dr_desc *desc, struct so2dr_plan **out);
+
+/* Release a plan (and the HIP events it created at bind time).  NULL is a no-op. */
+void so2dr_plan_destroy(struct so2dr_plan *plan);
+
+/* Planner outputs (host-only). */
+int so2dr_plan_get_info(const struct so2dr_plan *plan, so2dr_plan_info *info);
+
+/* Device bytes the caller must provide to so2dr_plan_bind (<= the budget). */
+int so2dr_plan_workspace_bytes(const struct so2dr_plan *plan, size_t *bytes);
+
+/* Copy the first n entries of the schedule into ops (host-only; n <= info.n_ops). */
+int so2dr_plan_get_ops(const struct so2dr_plan *plan, so2dr_op *ops, int64_t n);
+
+/* Attach device memory and streams.  dev_arena: device pointer to at least
+ * so2dr_plan_workspace_bytes bytes, 256-byte aligned, owned by the caller and
+ * not touched by anything else while a run is in flight.  streams: n_streams
+ * HIP streams (hipStream_t as void*), owned by the caller; chunk slot s uses
+ * streams[s % n_streams].  Creates the plan's HIP events.  The plan keeps the
+ * pointers, not the memory.  Errors: E_INVALID (null, misaligned or short
+ * arena), E_HIP. */
+int so2dr_plan_bind(struct so2dr_plan *plan, void *dev_arena, size_t arena_bytes,
+                    void *const *streams, int n_streams);
+
+/* Enable (1) or disable (0) per-operation HIP event timing in so2dr_stats. */
+int so2dr_plan_set_timing(struct so2dr_plan *plan, int enable);
+
+/* Run the plan's T steps: host_u holds u_0 on entry and u_T on return, in
+ * place (nx*ny*nz elements of the storage type, pinned).  Synchronous: the
+ * array may be reused when the call returns.  st may be NULL.
+ * Errors: E_UNBOUND, E_NOT_PINNED, E_HIP (host contents then undefined;
+ * st->rounds_done tells how many rounds completed). */
+int so2dr_run(struct so2dr_plan *plan, void *host_u, so2dr_stats *st);
+
+/* As so2dr_run but out of place and for `steps` steps (0 < steps <= T, same
+ * chunking and depth): host_in is read-only, host_out receives u_steps.
+ * host_in == host_out is the in-place run. */
+int so2dr_run_steps(struct so2dr_plan *plan, const void *host_in, void *host_out, int steps,
+                    so2dr_stats *st);
+
+/* Adjoint of the whole sweep for L = 1/2 sum_x (u_T(x) - target(x))^2
+ * (not in the paper; the transpose map of the same stencil, run backwards in
+ * time with the same out-of-core machinery).  host_u0, host_target: inputs
+ * (pinned, storage type F32 or F64).  host_grad_u0 receives dL/du_0; grad_w
+ * receives n_weights doubles dL/dw (lexicographic order); *loss receives L.
+ * The forward states at every ckpt_every-th step are kept in the caller's
+ * pinned host buffers host_ckpt[0..n_ckpt-1] (each one field) and recomputed
+ * in between.  n_ckpt must be >= ceil(T / ckpt_every).  Loss and weight
+ * gradients are accumulated in FP64 on the GPU.
+ * Errors: E_UNBOUND, E_NOT_PINNED, E_INVALID, E_UNSUPPORTED, E_HIP. */
+int so2dr_adjoint_run(struct so2dr_plan *plan, const void *host_u0, const void *host_target,
+                      void *host_grad_u0, double *grad_w, double *loss, int ckpt_every,
+                      void *const *host_ckpt, int n_ckpt, so2dr_stats *st);
+
+/* Message describing the last error on this thread ("" if none). */
+const char *so2dr_last_error(void);
+
+/* Library version string. */
+const char *so2dr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SO2DR_H */

@@ -1,0 +1,110 @@
+"""ctypes view of the C interface declared in include/so2dr.h.
+
+Argument marshalling only: every step of the sweep runs inside libso2dr.so.
+Loading fails loudly when the library has not been built."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libso2dr.so")
+
+OK, E_INVALID, E_BUDGET, E_UNSUPPORTED, E_NOT_PINNED, E_HIP, E_UNBOUND = 0, -1, -2, -3, -4, -5, -6
+ERROR_NAMES = {E_INVALID: "E_INVALID", E_BUDGET: "E_BUDGET", E_UNSUPPORTED: "E_UNSUPPORTED",
+               E_NOT_PINNED: "E_NOT_PINNED", E_HIP: "E_HIP", E_UNBOUND: "E_UNBOUND"}
+DTYPES = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3}
+SHAPES = {"star": 0, "box": 1}
+OP_KINDS = {0: "H2D", 1: "RS_READ", 2: "RS_WRITE", 3: "KERNEL", 4: "D2H"}
+
+# Symbols the header declares; the CPU test checks each is exported.
+EXPORTS = ["so2dr_plan_create", "so2dr_plan_destroy", "so2dr_plan_get_info",
+           "so2dr_plan_workspace_bytes", "so2dr_plan_get_ops", "so2dr_plan_bind",
+           "so2dr_plan_set_timing", "so2dr_run", "so2dr_run_steps", "so2dr_adjoint_run",
+           "so2dr_last_error", "so2dr_version"]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("shape", ctypes.c_int), ("radius", ctypes.c_int),
+                ("weights", ctypes.POINTER(ctypes.c_double)), ("n_weights", ctypes.c_int),
+                ("bc", ctypes.c_int * 3), ("storage", ctypes.c_int), ("T", ctypes.c_int),
+                ("n_chunks", ctypes.c_int), ("tb_depth", ctypes.c_int), ("k_on", ctypes.c_int),
+                ("n_slots", ctypes.c_int), ("device_budget_bytes", ctypes.c_size_t),
+                ("adjoint", ctypes.c_int)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_axis", ctypes.c_int64), ("plane_elems", ctypes.c_int64),
+                ("n_chunks", ctypes.c_int), ("tb_depth", ctypes.c_int), ("k_on", ctypes.c_int),
+                ("n_slots", ctypes.c_int), ("n_rounds", ctypes.c_int),
+                ("max_chunk_planes", ctypes.c_int), ("slot_planes", ctypes.c_int),
+                ("max_k_on", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
+                ("slot_bytes", ctypes.c_size_t), ("rs_bytes", ctypes.c_size_t),
+                ("scratch_bytes", ctypes.c_size_t), ("redundant_fraction", ctypes.c_double),
+                ("n_ops", ctypes.c_int64)]
+
+
+class Op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("round", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("slot", ctypes.c_int), ("z0", ctypes.c_int64), ("z1", ctypes.c_int64),
+                ("in_z0", ctypes.c_int64), ("in_z1", ctypes.c_int64), ("level_in", ctypes.c_int),
+                ("levels", ctypes.c_int), ("buf_in", ctypes.c_int), ("buf_out", ctypes.c_int),
+                ("buf_z0", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("h2d_ms", ctypes.c_double),
+                ("d2h_ms", ctypes.c_double), ("d2d_ms", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("bytes_h2d", ctypes.c_uint64),
+                ("bytes_d2h", ctypes.c_uint64), ("bytes_d2d", ctypes.c_uint64),
+                ("kernel_launches", ctypes.c_uint64), ("cell_updates", ctypes.c_uint64),
+                ("cell_updates_done", ctypes.c_uint64), ("kernel_alg_bytes", ctypes.c_uint64),
+                ("rounds_done", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2309_08864_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        L.so2dr_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+        L.so2dr_plan_destroy.argtypes = [vp]
+        L.so2dr_plan_destroy.restype = None
+        L.so2dr_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.so2dr_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.so2dr_plan_get_ops.argtypes = [vp, ctypes.POINTER(Op), i64]
+        L.so2dr_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp), i32]
+        L.so2dr_plan_set_timing.argtypes = [vp, i32]
+        L.so2dr_run.argtypes = [vp, vp, ctypes.POINTER(Stats)]
+        L.so2dr_run_steps.argtypes = [vp, vp, vp, i32, ctypes.POINTER(Stats)]
+        L.so2dr_adjoint_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(vp),
+                                        i32, ctypes.POINTER(Stats)]
+        L.so2dr_last_error.restype = ctypes.c_char_p
+        L.so2dr_version.restype = ctypes.c_char_p
+        for f in ("so2dr_plan_create", "so2dr_plan_get_info", "so2dr_plan_workspace_bytes",
+                  "so2dr_plan_get_ops", "so2dr_plan_bind", "so2dr_plan_set_timing", "so2dr_run",
+                  "so2dr_run_steps", "so2dr_adjoint_run"):
+            getattr(L, f).restype = i32
+        _LIB = L
+    return _LIB
+
+
+class So2drError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc != 0:
+        raise So2drError(rc, lib().so2dr_last_error().decode())
+    return rc

@@ -1,0 +1,193 @@
+// capi.cpp -- the extern "C" boundary.  Every entry point validates its
+// arguments, catches every C++ exception and reports failures through a
+// return code plus a thread-local message.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "plan.hpp"
+
+struct so2dr_plan {
+  so2dr::Plan p;
+};
+
+namespace so2dr {
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+int bind_plan(Plan &P, void *arena, size_t bytes, void *const *streams, int n_streams);
+int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats *st);
+int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, double *grad_w,
+                double *loss, int ckpt_every, void *const *ckpt, int n_ckpt, so2dr_stats *st);
+}  // namespace so2dr
+
+using so2dr::set_error;
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                            \
+  }                                                          \
+  catch (const std::bad_alloc &) {                           \
+    set_error("host allocation failed");                     \
+    return SO2DR_E_INVALID;                                  \
+  }                                                          \
+  catch (const std::exception &e) {                          \
+    set_error(std::string("internal error: ") + e.what());   \
+    return SO2DR_E_INVALID;                                  \
+  }                                                          \
+  catch (...) {                                              \
+    set_error("internal error");                             \
+    return SO2DR_E_INVALID;                                  \
+  }
+
+extern "C" {
+
+int so2dr_plan_create(const so2dr_desc *desc, so2dr_plan **out) {
+  GUARD_BEGIN
+  if (!desc || !out) {
+    set_error("null descriptor or output pointer");
+    return SO2DR_E_INVALID;
+  }
+  *out = nullptr;
+  so2dr_plan *h = new so2dr_plan();
+  const int rc = so2dr::make_plan(*desc, &h->p);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  set_error("");
+  return SO2DR_OK;
+  GUARD_END
+}
+
+void so2dr_plan_destroy(so2dr_plan *plan) {
+  try {
+    delete plan;
+  } catch (...) {
+  }
+}
+
+int so2dr_plan_get_info(const so2dr_plan *plan, so2dr_plan_info *info) {
+  GUARD_BEGIN
+  if (!plan || !info) {
+    set_error("null plan or info");
+    return SO2DR_E_INVALID;
+  }
+  const so2dr::Plan &P = plan->p;
+  std::memset(info, 0, sizeof(*info));
+  info->n_axis = P.N;
+  info->plane_elems = P.plane;
+  info->n_chunks = P.d;
+  info->tb_depth = P.K;
+  info->k_on = P.k_on;
+  info->n_slots = P.n_slots;
+  info->n_rounds = so2dr::n_rounds_for(P, P.T);
+  int64_t mx = 0;
+  for (int i = 0; i < P.d; ++i) mx = std::max<int64_t>(mx, P.bnd[i + 1] - P.bnd[i]);
+  info->max_chunk_planes = (int)mx;
+  info->slot_planes = (int)P.slot_planes;
+  info->max_k_on = P.max_k_on;
+  info->workspace_bytes = P.workspace;
+  info->slot_bytes = 2 * P.buf_bytes;
+  info->rs_bytes = P.rs_bytes;
+  info->scratch_bytes = P.scratch_bytes;
+  int64_t computed = 0;
+  auto ops = so2dr::build_ops(P, P.T, &computed);
+  info->n_ops = (int64_t)ops.size();
+  const double useful = (double)P.N * (double)P.T;
+  info->redundant_fraction = useful > 0 ? (double)computed / useful - 1.0 : 0.0;
+  return SO2DR_OK;
+  GUARD_END
+}
+
+int so2dr_plan_workspace_bytes(const so2dr_plan *plan, size_t *bytes) {
+  GUARD_BEGIN
+  if (!plan || !bytes) {
+    set_error("null plan or output");
+    return SO2DR_E_INVALID;
+  }
+  *bytes = plan->p.workspace;
+  return SO2DR_OK;
+  GUARD_END
+}
+
+int so2dr_plan_get_ops(const so2dr_plan *plan, so2dr_op *ops, int64_t n) {
+  GUARD_BEGIN
+  if (!plan || (!ops && n > 0) || n < 0) {
+    set_error("null plan or ops");
+    return SO2DR_E_INVALID;
+  }
+  auto all = so2dr::build_ops(plan->p, plan->p.T, nullptr);
+  if (n > (int64_t)all.size()) {
+    set_error("n exceeds the schedule length");
+    return SO2DR_E_INVALID;
+  }
+  if (n > 0) std::memcpy(ops, all.data(), sizeof(so2dr_op) * (size_t)n);
+  return SO2DR_OK;
+  GUARD_END
+}
+
+int so2dr_plan_bind(so2dr_plan *plan, void *dev_arena, size_t arena_bytes, void *const *streams,
+                    int n_streams) {
+  GUARD_BEGIN
+  if (!plan) {
+    set_error("null plan");
+    return SO2DR_E_INVALID;
+  }
+  return so2dr::bind_plan(plan->p, dev_arena, arena_bytes, streams, n_streams);
+  GUARD_END
+}
+
+int so2dr_plan_set_timing(so2dr_plan *plan, int enable) {
+  GUARD_BEGIN
+  if (!plan) {
+    set_error("null plan");
+    return SO2DR_E_INVALID;
+  }
+  plan->p.timing = enable != 0;
+  return SO2DR_OK;
+  GUARD_END
+}
+
+int so2dr_run(so2dr_plan *plan, void *host_u, so2dr_stats *st) {
+  GUARD_BEGIN
+  if (!plan) {
+    set_error("null plan");
+    return SO2DR_E_INVALID;
+  }
+  return so2dr::execute(plan->p, host_u, host_u, plan->p.T, st);
+  GUARD_END
+}
+
+int so2dr_run_steps(so2dr_plan *plan, const void *host_in, void *host_out, int steps,
+                    so2dr_stats *st) {
+  GUARD_BEGIN
+  if (!plan) {
+    set_error("null plan");
+    return SO2DR_E_INVALID;
+  }
+  if (steps < 1) {
+    set_error("steps must be >= 1");
+    return SO2DR_E_INVALID;
+  }
+  return so2dr::execute(plan->p, host_in, host_out, steps, st);
+  GUARD_END
+}
+
+int so2dr_adjoint_run(so2dr_plan *plan, const void *host_u0, const void *host_target,
+                      void *host_grad_u0, double *grad_w, double *loss, int ckpt_every,
+                      void *const *host_ckpt, int n_ckpt, so2dr_stats *st) {
+  GUARD_BEGIN
+  if (!plan) {
+    set_error("null plan");
+    return SO2DR_E_INVALID;
+  }
+  return so2dr::adjoint_run(plan->p, host_u0, host_target, host_grad_u0, grad_w, loss,
+                            ckpt_every, host_ckpt, n_ckpt, st);
+  GUARD_END
+}
+
+const char *so2dr_last_error(void) { return so2dr::g_err.c_str(); }
+
+const char *so2dr_version(void) { return "so2dr-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

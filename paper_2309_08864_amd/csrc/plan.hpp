@@ -1,0 +1,68 @@
+// plan.hpp -- host-side plan: geometry, schedule and bound device state.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/so2dr.h"
+
+namespace so2dr {
+
+void set_error(const std::string &msg);
+
+struct Plan {
+  // ---- problem (validated copy of the descriptor)
+  int ndim = 0, shape = 0, r = 0, dtype = 0, stencil = -1;
+  int64_t nx = 0, ny = 0, nz = 0;
+  int64_t NX = 0, NY = 0, N = 0;   // in-plane extents and cut-axis length
+  int64_t plane = 0;               // elements per plane
+  size_t elem = 0;                 // bytes per stored element
+  int per_x = 0, per_y = 0;        // periodic flags of the in-plane axes
+  std::vector<double> weights;     // lexicographic
+  // ---- plan
+  int T = 0, K = 0, k_on = 0, d = 0, n_slots = 0, max_k_on = 0;
+  std::vector<int64_t> bnd;        // chunk i owns planes [bnd[i], bnd[i+1])
+  int64_t slot_planes = 0;
+  size_t buf_bytes = 0;            // one ping-pong buffer (256-aligned)
+  size_t rs_bytes = 0, scratch_bytes = 0, workspace = 0, budget = 0;
+  size_t adj_bytes = 0;            // extra space reserved for the adjoint
+  bool adjoint = false;
+  // ---- bound state
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  std::vector<hipStream_t> streams;
+  bool bound = false;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_rs, ev_d2h;   // indexed by round * d + chunk
+  std::vector<hipEvent_t> ev_t;            // timing pairs, 2 per op
+  ~Plan();
+
+  size_t plane_bytes() const { return (size_t)plane * elem; }
+  char *slot_buf(int slot, int which) const {
+    return arena + ((size_t)slot * 2 + (size_t)which) * buf_bytes;
+  }
+  char *rs_pool() const { return arena + (size_t)n_slots * 2 * buf_bytes; }
+  char *scratch() const { return rs_pool() + rs_bytes; }
+};
+
+// Geometry of round `t` for a run of `steps` steps.
+int round_depth(const Plan &P, int steps, int t);
+int n_rounds_for(const Plan &P, int steps);
+// Valid planes of chunk i at level s of a round of depth kp (Sec. IV-B).
+int64_t area_lo(const Plan &P, int i, int kp, int s);
+int64_t area_hi(const Plan &P, int i, int kp, int s);
+
+// Build the schedule for `steps` steps (Algorithm 1 unrolled).  Also returns
+// the number of cell-plane updates computed (including redundant ones).
+std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_computed);
+
+// Validate and plan; returns 0 or a negative code with set_error().
+int make_plan(const so2dr_desc &d, Plan *out);
+
+size_t dtype_size(int dtype);
+int stencil_id(int ndim, int shape, int r);
+int expected_points(int ndim, int shape, int r);
+
+}  // namespace so2dr

@@ -1,0 +1,257 @@
+// runtime.cpp -- the executor: runs a plan's schedule on HIP streams.
+//
+// Streams and ordering (Algorithm 1's "chunks are assigned to different
+// streams", Sec. IV-A).  Slot s of the plan runs on the caller's stream
+// s mod n_streams, so a slot's reuse by a later chunk is ordered by its stream.
+// Cross-stream dependencies are HIP events:
+//   * region sharing: the buffer ops of consecutive chunks (in round-major
+//     order) form a chain, so chunk i reads what chunk i-1 wrote before chunk
+//     i overwrites it (read, then write);
+//   * host array, in place across rounds: round t+1's copy-in of chunk i
+//     waits for round t's copy-out of chunks i and i+1, which together write
+//     the planes it reads.
+// Within a round, chunk i's copy-out (which overwrites r k' planes below its
+// own range) is ordered after chunk i-1's copy-in through the same chain.
+// Nothing synchronises the device between rounds.
+#include <chrono>
+#include <cstring>
+
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace so2dr {
+
+Plan::~Plan() {
+  for (auto e : ev_rs) hipEventDestroy(e);
+  for (auto e : ev_d2h) hipEventDestroy(e);
+  for (auto e : ev_t) hipEventDestroy(e);
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+      return SO2DR_E_HIP;                                                             \
+    }                                                                                 \
+  } while (0)
+
+static int ensure_events(std::vector<hipEvent_t> &v, size_t n, unsigned flags) {
+  while (v.size() < n) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, flags));
+    v.push_back(e);
+  }
+  return SO2DR_OK;
+}
+
+int check_pinned(const void *p, size_t bytes, const char *what) {
+  if (!p) {
+    set_error(std::string(what) + " is null");
+    return SO2DR_E_INVALID;
+  }
+  const char *c = static_cast<const char *>(p);
+  for (const char *q : {c, c + (bytes ? bytes - 1 : 0)}) {
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof(a));
+    hipError_t e = hipPointerGetAttributes(&a, q);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error(std::string(what) + " is not pinned host memory");
+      return SO2DR_E_NOT_PINNED;
+    }
+    if (a.type != hipMemoryTypeHost) {
+      set_error(std::string(what) + " is not pinned host memory");
+      return SO2DR_E_NOT_PINNED;
+    }
+  }
+  return SO2DR_OK;
+}
+
+int bind_plan(Plan &P, void *arena, size_t bytes, void *const *streams, int n_streams) {
+  if (!arena || (reinterpret_cast<uintptr_t>(arena) & 255)) {
+    set_error("arena must be a non-null 256-byte aligned device pointer");
+    return SO2DR_E_INVALID;
+  }
+  if (bytes < P.workspace) {
+    set_error("arena smaller than the plan's workspace");
+    return SO2DR_E_INVALID;
+  }
+  if (!streams || n_streams < 1) {
+    set_error("at least one stream is needed");
+    return SO2DR_E_INVALID;
+  }
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, arena) != hipSuccess || a.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    set_error("arena is not device memory");
+    return SO2DR_E_INVALID;
+  }
+  P.arena = static_cast<char *>(arena);
+  P.arena_bytes = bytes;
+  P.streams.clear();
+  for (int i = 0; i < n_streams; ++i) P.streams.push_back(static_cast<hipStream_t>(streams[i]));
+  P.bound = true;
+  return SO2DR_OK;
+}
+
+// Run `steps` steps from host_in into host_out (may alias).
+int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats *st) {
+  if (!P.bound) {
+    set_error("plan is not bound to device memory and streams");
+    return SO2DR_E_UNBOUND;
+  }
+  if (steps < 0 || steps > P.T) {
+    set_error("steps must be in [0, T]");
+    return SO2DR_E_INVALID;
+  }
+  const size_t field = (size_t)P.N * P.plane_bytes();
+  int rc = check_pinned(host_in, field, "input host array");
+  if (rc) return rc;
+  rc = check_pinned(host_out, field, "output host array");
+  if (rc) return rc;
+  so2dr_stats S;
+  std::memset(&S, 0, sizeof(S));
+  const auto t_start = std::chrono::steady_clock::now();
+  if (steps == 0) {
+    if (host_in != host_out) std::memcpy(host_out, host_in, field);
+    if (st) *st = S;
+    return SO2DR_OK;
+  }
+  int64_t computed = 0;
+  const std::vector<so2dr_op> ops = build_ops(P, steps, &computed);
+  const int nt = n_rounds_for(P, steps);
+  const size_t nseq = (size_t)nt * P.d;
+  rc = ensure_events(P.ev_rs, nseq, hipEventDisableTiming);
+  if (rc) return rc;
+  rc = ensure_events(P.ev_d2h, nseq, hipEventDisableTiming);
+  if (rc) return rc;
+  if (P.timing) {
+    rc = ensure_events(P.ev_t, 2 * ops.size(), hipEventDefault);
+    if (rc) return rc;
+  }
+  const size_t pb = P.plane_bytes();
+  const char *hin = static_cast<const char *>(host_in);
+  char *hout = static_cast<char *>(host_out);
+  std::string msg;
+  int prev_rs_chunk = -1;  // global sequence index of the last chunk with RS ops
+  int rs_open = -1;        // sequence index whose RS ops are being enqueued
+  for (size_t k = 0; k < ops.size(); ++k) {
+    const so2dr_op &op = ops[k];
+    const int g = op.round * P.d + op.chunk;
+    hipStream_t s = P.streams[op.slot % P.streams.size()];
+    // close the RS group of a chunk once its first non-RS op after it comes
+    if (rs_open >= 0 && !(op.kind == SO2DR_OP_RS_READ || op.kind == SO2DR_OP_RS_WRITE)) {
+      hipStream_t rs_s = P.streams[ops[k - 1].slot % P.streams.size()];
+      HIPCHK(hipEventRecord(P.ev_rs[rs_open], rs_s));
+      prev_rs_chunk = rs_open;
+      rs_open = -1;
+    }
+    if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k], s));
+    switch (op.kind) {
+      case SO2DR_OP_H2D: {
+        if (op.round > 0) {
+          HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.d], 0));
+          if (op.chunk + 1 < P.d) HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.d + 1], 0));
+        }
+        const char *src = (op.round == 0 ? hin : hout) + (size_t)op.z0 * pb;
+        char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
+        HIPCHK(hipMemcpyAsync(dst, src, (size_t)(op.z1 - op.z0) * pb, hipMemcpyHostToDevice, s));
+        S.bytes_h2d += (uint64_t)(op.z1 - op.z0) * pb;
+        break;
+      }
+      case SO2DR_OP_RS_READ:
+      case SO2DR_OP_RS_WRITE: {
+        if (rs_open < 0) {
+          if (prev_rs_chunk >= 0) HIPCHK(hipStreamWaitEvent(s, P.ev_rs[prev_rs_chunk], 0));
+          rs_open = g;
+        }
+        const size_t n = (size_t)(op.z1 - op.z0) * pb;
+        if (op.kind == SO2DR_OP_RS_READ) {
+          char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
+          HIPCHK(hipMemcpyAsync(dst, P.rs_pool(), n, hipMemcpyDeviceToDevice, s));
+        } else {
+          const char *src = P.slot_buf(op.slot, op.buf_in) + (size_t)(op.z0 - op.buf_z0) * pb;
+          HIPCHK(hipMemcpyAsync(P.rs_pool(), src, n, hipMemcpyDeviceToDevice, s));
+        }
+        S.bytes_d2d += n;
+        break;
+      }
+      case SO2DR_OP_KERNEL: {
+        LaunchParams lp;
+        lp.stencil = P.stencil;
+        lp.kl = op.levels;
+        lp.in = P.slot_buf(op.slot, op.buf_in);
+        lp.out = P.slot_buf(op.slot, op.buf_out);
+        lp.buf_z0 = op.buf_z0;
+        lp.plane = P.plane;
+        lp.nx = (int)P.NX;
+        lp.ny = (int)P.NY;
+        lp.per_x = P.per_x;
+        lp.per_y = P.per_y;
+        lp.n_axis = P.N;
+        lp.in_lo = op.in_z0;
+        lp.in_hi = op.in_z1;
+        lp.out_lo = op.z0;
+        lp.out_hi = op.z1;
+        lp.weights = P.weights.data();
+        lp.npts = (int)P.weights.size();
+        rc = launch_tb(P.dtype, lp, s, &msg);
+        if (rc) {
+          set_error(msg);
+          return rc;
+        }
+        S.kernel_launches += 1;
+        S.kernel_alg_bytes += (uint64_t)((op.in_z1 - op.in_z0) + (op.z1 - op.z0)) * pb;
+        break;
+      }
+      case SO2DR_OP_D2H: {
+        const char *src = P.slot_buf(op.slot, op.buf_in) + (size_t)(op.z0 - op.buf_z0) * pb;
+        HIPCHK(hipMemcpyAsync(hout + (size_t)op.z0 * pb, src, (size_t)(op.z1 - op.z0) * pb,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(P.ev_d2h[g], s));
+        S.bytes_d2h += (uint64_t)(op.z1 - op.z0) * pb;
+        if (op.chunk == P.d - 1) S.rounds_done = op.round + 1;
+        break;
+      }
+      default:
+        set_error("corrupt schedule");
+        return SO2DR_E_INVALID;
+    }
+    if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k + 1], s));
+  }
+  for (hipStream_t s : P.streams) HIPCHK(hipStreamSynchronize(s));
+  const auto t_end = std::chrono::steady_clock::now();
+  S.wall_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+  S.cell_updates = (uint64_t)P.N * (uint64_t)P.plane * (uint64_t)steps;
+  S.cell_updates_done = (uint64_t)computed * (uint64_t)P.plane;
+  if (P.timing) {
+    for (size_t k = 0; k < ops.size(); ++k) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, P.ev_t[2 * k], P.ev_t[2 * k + 1]));
+      switch (ops[k].kind) {
+        case SO2DR_OP_H2D: S.h2d_ms += ms; break;
+        case SO2DR_OP_D2H: S.d2h_ms += ms; break;
+        case SO2DR_OP_KERNEL: S.kernel_ms += ms; break;
+        default: S.d2d_ms += ms; break;
+      }
+    }
+  }
+  if (st) *st = S;
+  return SO2DR_OK;
+}
+
+int launch_tb(int dtype, const LaunchParams &p, hipStream_t stream, std::string *msg) {
+  switch (dtype) {
+    case SO2DR_F32: return launch_tb_f32(p, stream, msg);
+    case SO2DR_F64: return launch_tb_f64(p, stream, msg);
+    case SO2DR_BF16: return launch_tb_bf16(p, stream, msg);
+    case SO2DR_F16: return launch_tb_f16(p, stream, msg);
+    default:
+      if (msg) *msg = "unknown storage type";
+      return SO2DR_E_INVALID;
+  }
+}
+
+}  // namespace so2dr

@@ -1,0 +1,127 @@
+"""Python face of the library: build a plan, give it device memory and
+streams from PyTorch, run it on pinned host tensors.
+
+PyTorch supplies only the device arena (one uint8 tensor of the plan's
+workspace size), the HIP streams and pinned host tensors; the planner,
+executor and kernels are the native library's."""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import DTYPES, OP_KINDS, SHAPES, check, lib
+
+TORCH_DTYPES = {"f32": "float32", "f64": "float64", "bf16": "bfloat16", "f16": "float16"}
+
+
+def stencil_offsets(ndim, shape, r):
+    """(dz, dy, dx) offsets of a star or box stencil in the lexicographic order
+    the weight array uses (2D stencils have dz == 0; their rows are the cut
+    axis)."""
+    rng = range(-r, r + 1)
+    pts = []
+    for a in (rng if ndim == 3 else (0,)):
+        for b in rng:
+            for c in rng:
+                if shape == "box" or (a != 0) + (b != 0) + (c != 0) <= 1:
+                    pts.append((a, b, c))
+    return pts
+
+
+class Plan:
+    """A planned out-of-core sweep.
+
+    Grid extents are (nx, ny, nz) with x contiguous; a 2D grid has nz == 1
+    and is cut along y.  ``weights`` follows stencil_offsets' order.
+    ``bc`` gives, per axis x, y, z, 0 for zero Dirichlet or 1 for periodic."""
+
+    def __init__(self, *, ndim, nx, ny, nz=1, shape="star", radius=1, weights, T, tb_depth=0,
+                 n_chunks=0, k_on=0, n_slots=0, budget, storage="f32", bc=(0, 0, 0),
+                 adjoint=False):
+        self.storage = storage
+        self.shape3 = (nz, ny, nx)
+        self._w = (ctypes.c_double * len(weights))(*[float(x) for x in weights])
+        d = _lib.Desc()
+        d.ndim, d.nx, d.ny, d.nz = ndim, nx, ny, nz
+        d.shape, d.radius = SHAPES[shape], radius
+        d.weights = ctypes.cast(self._w, ctypes.POINTER(ctypes.c_double))
+        d.n_weights = len(weights)
+        d.bc = (ctypes.c_int * 3)(*bc)
+        d.storage = DTYPES[storage]
+        d.T, d.n_chunks, d.tb_depth, d.k_on, d.n_slots = T, n_chunks, tb_depth, k_on, n_slots
+        d.device_budget_bytes = int(budget)
+        d.adjoint = 1 if adjoint else 0
+        h = ctypes.c_void_p()
+        check(lib().so2dr_plan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._arena = None
+        self._streams = None
+
+    # ------------------------------------------------------------ host-only
+    def info(self):
+        i = _lib.PlanInfo()
+        check(lib().so2dr_plan_get_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in i._fields_}
+
+    def ops(self):
+        n = self.info()["n_ops"]
+        arr = (_lib.Op * max(n, 1))()
+        check(lib().so2dr_plan_get_ops(self._h, arr, n))
+        out = []
+        for k in range(n):
+            o = arr[k]
+            d = {f: getattr(o, f) for f, _ in o._fields_}
+            d["kind"] = OP_KINDS[d["kind"]]
+            out.append(d)
+        return out
+
+    # ------------------------------------------------------------ device
+    def bind(self, device="cuda", n_streams=None):
+        import torch
+        ws = self.info()["workspace_bytes"]
+        self._arena = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+        ns = n_streams or max(1, self.info()["n_slots"])
+        self._streams = [torch.cuda.Stream(device=device) for _ in range(ns)]
+        arr = (ctypes.c_void_p * ns)(*[s.cuda_stream for s in self._streams])
+        check(lib().so2dr_plan_bind(self._h, ctypes.c_void_p(self._arena.data_ptr()),
+                                    self._arena.numel(), arr, ns))
+        return self
+
+    def set_timing(self, enable=True):
+        check(lib().so2dr_plan_set_timing(self._h, 1 if enable else 0))
+
+    def run(self, host_u):
+        """In place: host_u (pinned tensor of the storage dtype) u_0 -> u_T."""
+        self._check_host(host_u)
+        st = _lib.Stats()
+        check(lib().so2dr_run(self._h, ctypes.c_void_p(host_u.data_ptr()), ctypes.byref(st)))
+        return st.as_dict()
+
+    def run_steps(self, host_in, host_out, steps):
+        self._check_host(host_in)
+        self._check_host(host_out)
+        st = _lib.Stats()
+        check(lib().so2dr_run_steps(self._h, ctypes.c_void_p(host_in.data_ptr()),
+                                    ctypes.c_void_p(host_out.data_ptr()), int(steps),
+                                    ctypes.byref(st)))
+        return st.as_dict()
+
+    def _check_host(self, t):
+        import torch
+        if t.dtype != getattr(torch, TORCH_DTYPES[self.storage]):
+            raise TypeError(f"host array must be {TORCH_DTYPES[self.storage]}")
+        if not t.is_contiguous() or t.numel() != int(np.prod(self.shape3)):
+            raise ValueError("host array must be contiguous with nx*ny*nz elements")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().so2dr_plan_destroy(self._h)
+            self._h = None
+        self._arena = None
+        self._streams = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
