@@ -192,7 +192,7 @@ def main():
     plan.close()
     del h
     if not args.no_cpu_baseline:
-        planes = args.cpu_sample_planes or 16
+        planes = args.cpu_sample_planes or 64
         res["cpu_baseline"] = cpu_baseline(wl, offs, w, planes)
     print(json.dumps(res), flush=True)
 

@@ -150,10 +150,13 @@ int so2dr_plan_get_ops(const struct so2dr_plan *plan, so2dr_op *ops, int64_t n);
 /* Attach device memory and streams.  dev_arena: device pointer to at least
  * so2dr_plan_workspace_bytes bytes, 256-byte aligned, owned by the caller and
  * not touched by anything else while a run is in flight.  streams: n_streams
- * HIP streams (hipStream_t as void*), owned by the caller; chunk slot s uses
- * streams[s % n_streams].  Creates the plan's HIP events.  The plan keeps the
- * pointers, not the memory.  Errors: E_INVALID (null, misaligned or short
- * arena), E_HIP. */
+ * HIP streams (hipStream_t as void*) at default priority, owned by the
+ * caller.  Roles: streams[0] carries every host -> HBM copy in order,
+ * streams[1] every HBM -> host copy, streams[2..n-1] the region-sharing
+ * copies and kernels (chunk g on streams[2 + g % (n-2)]).  With n_streams == 2
+ * the kernels share streams[0]; with 1 everything runs in order on it.
+ * Recommended: 3 (one compute stream) or 4.  The plan keeps the pointers, not
+ * the memory.  Errors: E_INVALID (null, misaligned or short arena), E_HIP. */
 int so2dr_plan_bind(struct so2dr_plan *plan, void *dev_arena, size_t arena_bytes,
                     void *const *streams, int n_streams);
 

@@ -35,7 +35,7 @@ struct Plan {
   std::vector<hipStream_t> streams;
   bool bound = false;
   bool timing = false;
-  std::vector<hipEvent_t> ev_rs, ev_d2h;   // indexed by round * d + chunk
+  std::vector<hipEvent_t> ev_rs, ev_d2h, ev_h2d, ev_comp;   // indexed by round * d + chunk
   std::vector<hipEvent_t> ev_t;            // timing pairs, 2 per op
   ~Plan();
 

@@ -1,17 +1,28 @@
 // runtime.cpp -- the executor: runs a plan's schedule on HIP streams.
 //
-// Streams and ordering (Algorithm 1's "chunks are assigned to different
-// streams", Sec. IV-A).  Slot s of the plan runs on the caller's stream
-// s mod n_streams, so a slot's reuse by a later chunk is ordered by its stream.
-// Cross-stream dependencies are HIP events:
-//   * region sharing: the buffer ops of consecutive chunks (in round-major
-//     order) form a chain, so chunk i reads what chunk i-1 wrote before chunk
-//     i overwrites it (read, then write);
+// Streams (Algorithm 1 spreads chunks over streams so that copy-in, kernels
+// and copy-out of different chunks overlap, Sec. IV-A and Sec. III).  On
+// MI355X the host link is the scarce resource and each direction has its own
+// DMA engine, so the executor gives each direction one in-order stream:
+//   streams[0]        copy-in (host -> HBM), one chunk after another;
+//   streams[1]        copy-out (HBM -> host), one chunk after another;
+//   streams[2..n-1]   compute: region-sharing copies and fused kernels,
+//                     chunk g on compute stream g mod (n - 2).
+// With fewer streams the roles share: n = 2 puts compute on the copy-in
+// stream, n = 1 runs everything in order on one stream.  Two copies never
+// split one direction's bandwidth, and kernels of consecutive chunks may
+// overlap each other when there are several compute streams (Sec. V-D).
+// Dependencies are HIP events:
+//   * copy-in of chunk g waits copy-out of chunk g - n_slots (slot reuse);
+//   * compute of g waits its copy-in; copy-out of g waits its compute;
+//   * region sharing: the buffer operations of consecutive chunks (in
+//     round-major order) form a chain, so chunk i reads what chunk i-1 wrote
+//     before chunk i overwrites it (read, then write, as Algorithm 1 says);
 //   * host array, in place across rounds: round t+1's copy-in of chunk i
-//     waits for round t's copy-out of chunks i and i+1, which together write
-//     the planes it reads.
-// Within a round, chunk i's copy-out (which overwrites r k' planes below its
-// own range) is ordered after chunk i-1's copy-in through the same chain.
+//     waits round t's copy-out of chunks i and i+1, which write the planes it
+//     reads.  Within a round, chunk i's copy-out (which overwrites r k'
+//     planes below its own range) follows chunk i-1's copy-in through the
+//     region-sharing chain.
 // Nothing synchronises the device between rounds.
 #include <chrono>
 #include <cstring>
@@ -24,6 +35,8 @@ namespace so2dr {
 Plan::~Plan() {
   for (auto e : ev_rs) hipEventDestroy(e);
   for (auto e : ev_d2h) hipEventDestroy(e);
+  for (auto e : ev_h2d) hipEventDestroy(e);
+  for (auto e : ev_comp) hipEventDestroy(e);
   for (auto e : ev_t) hipEventDestroy(e);
 }
 
@@ -131,30 +144,62 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
     rc = ensure_events(P.ev_t, 2 * ops.size(), hipEventDefault);
     if (rc) return rc;
   }
+  rc = ensure_events(P.ev_h2d, nseq, hipEventDisableTiming);
+  if (rc) return rc;
+  rc = ensure_events(P.ev_comp, nseq, hipEventDisableTiming);
+  if (rc) return rc;
   const size_t pb = P.plane_bytes();
   const char *hin = static_cast<const char *>(host_in);
   char *hout = static_cast<char *>(host_out);
+  const int ns = (int)P.streams.size();
+  hipStream_t s_in = P.streams[0];
+  hipStream_t s_out = ns >= 2 ? P.streams[1] : P.streams[0];
+  const int nc = ns >= 3 ? ns - 2 : 1;
+  auto s_comp = [&](int g) { return ns >= 3 ? P.streams[2 + g % nc] : P.streams[0]; };
   std::string msg;
-  int prev_rs_chunk = -1;  // global sequence index of the last chunk with RS ops
-  int rs_open = -1;        // sequence index whose RS ops are being enqueued
+  int prev_rs = -1;  // sequence index of the last chunk whose RS ops were enqueued
+  int rs_open = -1;  // sequence index whose RS ops are being enqueued
+  int comp_g = -1;   // sequence index of the chunk whose compute ops are being enqueued
   for (size_t k = 0; k < ops.size(); ++k) {
     const so2dr_op &op = ops[k];
     const int g = op.round * P.d + op.chunk;
-    hipStream_t s = P.streams[op.slot % P.streams.size()];
-    // close the RS group of a chunk once its first non-RS op after it comes
-    if (rs_open >= 0 && !(op.kind == SO2DR_OP_RS_READ || op.kind == SO2DR_OP_RS_WRITE)) {
-      hipStream_t rs_s = P.streams[ops[k - 1].slot % P.streams.size()];
-      HIPCHK(hipEventRecord(P.ev_rs[rs_open], rs_s));
-      prev_rs_chunk = rs_open;
+    const bool is_rs = op.kind == SO2DR_OP_RS_READ || op.kind == SO2DR_OP_RS_WRITE;
+    hipStream_t s = op.kind == SO2DR_OP_H2D ? s_in : op.kind == SO2DR_OP_D2H ? s_out : s_comp(g);
+    if (rs_open >= 0 && !is_rs) {  // the chunk's RS group ended with the previous op
+      HIPCHK(hipEventRecord(P.ev_rs[rs_open], s_comp(rs_open)));
+      prev_rs = rs_open;
       rs_open = -1;
     }
-    if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k], s));
+    // cross-stream waits, enqueued before the op's timing start
     switch (op.kind) {
-      case SO2DR_OP_H2D: {
+      case SO2DR_OP_H2D:
+        if (g >= P.n_slots) HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.n_slots], 0));
         if (op.round > 0) {
           HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.d], 0));
           if (op.chunk + 1 < P.d) HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.d + 1], 0));
         }
+        break;
+      case SO2DR_OP_RS_READ:
+      case SO2DR_OP_RS_WRITE:
+      case SO2DR_OP_KERNEL:
+        if (comp_g != g) {  // first compute op of this chunk: its input is in HBM
+          HIPCHK(hipStreamWaitEvent(s, P.ev_h2d[g], 0));
+          comp_g = g;
+        }
+        if (is_rs && rs_open < 0) {
+          if (prev_rs >= 0) HIPCHK(hipStreamWaitEvent(s, P.ev_rs[prev_rs], 0));
+          rs_open = g;
+        }
+        break;
+      case SO2DR_OP_D2H:
+        HIPCHK(hipStreamWaitEvent(s, P.ev_comp[g], 0));
+        break;
+      default:
+        break;
+    }
+    if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k], s));
+    switch (op.kind) {
+      case SO2DR_OP_H2D: {
         const char *src = (op.round == 0 ? hin : hout) + (size_t)op.z0 * pb;
         char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
         HIPCHK(hipMemcpyAsync(dst, src, (size_t)(op.z1 - op.z0) * pb, hipMemcpyHostToDevice, s));
@@ -163,10 +208,6 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
       }
       case SO2DR_OP_RS_READ:
       case SO2DR_OP_RS_WRITE: {
-        if (rs_open < 0) {
-          if (prev_rs_chunk >= 0) HIPCHK(hipStreamWaitEvent(s, P.ev_rs[prev_rs_chunk], 0));
-          rs_open = g;
-        }
         const size_t n = (size_t)(op.z1 - op.z0) * pb;
         if (op.kind == SO2DR_OP_RS_READ) {
           char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
@@ -210,7 +251,6 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
         const char *src = P.slot_buf(op.slot, op.buf_in) + (size_t)(op.z0 - op.buf_z0) * pb;
         HIPCHK(hipMemcpyAsync(hout + (size_t)op.z0 * pb, src, (size_t)(op.z1 - op.z0) * pb,
                               hipMemcpyDeviceToHost, s));
-        HIPCHK(hipEventRecord(P.ev_d2h[g], s));
         S.bytes_d2h += (uint64_t)(op.z1 - op.z0) * pb;
         if (op.chunk == P.d - 1) S.rounds_done = op.round + 1;
         break;
@@ -220,6 +260,11 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
         return SO2DR_E_INVALID;
     }
     if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k + 1], s));
+    // completion events other streams wait on
+    if (op.kind == SO2DR_OP_H2D) HIPCHK(hipEventRecord(P.ev_h2d[g], s));
+    if (op.kind == SO2DR_OP_D2H) HIPCHK(hipEventRecord(P.ev_d2h[g], s));
+    // the op before a copy-out is the chunk's last compute op
+    if (k + 1 < ops.size() && ops[k + 1].kind == SO2DR_OP_D2H) HIPCHK(hipEventRecord(P.ev_comp[g], s));
   }
   for (hipStream_t s : P.streams) HIPCHK(hipStreamSynchronize(s));
   const auto t_end = std::chrono::steady_clock::now();

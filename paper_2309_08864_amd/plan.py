@@ -80,7 +80,7 @@ class Plan:
         import torch
         ws = self.info()["workspace_bytes"]
         self._arena = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
-        ns = n_streams or max(1, self.info()["n_slots"])
+        ns = n_streams or 3    # copy-in, copy-out, one compute stream
         self._streams = [torch.cuda.Stream(device=device) for _ in range(ns)]
         arr = (ctypes.c_void_p * ns)(*[s.cuda_stream for s in self._streams])
         check(lib().so2dr_plan_bind(self._h, ctypes.c_void_p(self._arena.data_ptr()),

@@ -142,8 +142,11 @@ def test_schedule_variants_bitwise():
     ref, _, _ = gpu_run(dict(base, tb_depth=T, n_chunks=1, k_on=1), us)
     err = rel_l2(ref.double().numpy(), oracle.sweep(us.double().numpy(), offs, w, T))
     assert err <= 1e-5
+    # ns: 1 = everything on one stream; 2 = compute shares the copy-in stream;
+    # 3 = one compute stream; 4, 5 = kernels of consecutive chunks overlap
     for K, d, k_on, slots, ns in [(4, 2, 3, 1, 1), (4, 3, 4, 2, 2), (5, 5, 2, 3, 3), (3, 7, 3, 3, 1),
-                                  (2, 15, 1, 2, 3), (11, 2, 4, 2, 2), (1, 30, 1, 3, 3)]:
+                                  (2, 15, 1, 2, 4), (11, 2, 4, 2, 5), (1, 30, 1, 3, 5),
+                                  (3, 9, 2, 3, 4)]:
         got, st, info = gpu_run(dict(base, tb_depth=K, n_chunks=d, k_on=k_on, n_slots=slots), us,
                                 bind_streams=ns)
         assert info["n_chunks"] == d and info["n_slots"] == slots
