@@ -11,8 +11,14 @@ namespace so2dr {
 
 // Workgroups a launch aims for before it splits the cut axis into segments;
 // each segment re-reads 2*KL*R input planes, so segments stay long.
-constexpr int64_t kTargetWgs = 1024;
-constexpr int64_t kMinSegPlanes = 16;
+#ifndef SO2DR_TARGET_WGS
+#define SO2DR_TARGET_WGS 1024
+#endif
+#ifndef SO2DR_MIN_SEG
+#define SO2DR_MIN_SEG 16
+#endif
+constexpr int64_t kTargetWgs = SO2DR_TARGET_WGS;
+constexpr int64_t kMinSegPlanes = SO2DR_MIN_SEG;
 
 template <typename T, int NDIM, bool BOX, int R, int KL>
 int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
@@ -63,7 +69,10 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
     }
     attr_done = true;
   }
-  hipLaunchKernelGGL((tb_kernel<T, NDIM, BOX, R, KL>), dim3((unsigned)nwg), dim3(G::NT), lds, stream, a);
+  // with the XCD-aware order the grid is padded to a multiple of 8 so that the
+  // permutation covers every tile; padding workgroups exit at once
+  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  hipLaunchKernelGGL((tb_kernel<T, NDIM, BOX, R, KL>), dim3((unsigned)grid), dim3(G::NT), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     if (msg) *msg = std::string("kernel launch: ") + hipGetErrorString(e);
