@@ -85,7 +85,7 @@ typedef struct {
   int slot_planes;            /* planes in one slot buffer */
   int max_k_on;               /* deepest fused kernel built for this stencil */
   size_t workspace_bytes;     /* everything the plan uses; <= budget */
-  size_t slot_bytes;          /* one slot = two ping-pong buffers */
+  size_t slot_bytes;          /* one slot: two ping-pong buffers (five with the adjoint) */
   size_t rs_bytes;            /* region-sharing buffer */
   size_t scratch_bytes;       /* reduction scratch (adjoint) */
   double redundant_fraction;  /* recomputed / useful cell updates */

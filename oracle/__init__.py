@@ -19,4 +19,5 @@ conservation laws, the adjoint dot-product identity and finite differences.
 """
 from .oracle import (  # noqa: F401
     stencil_offsets, sweep, transpose_step, adjoint, sweep_box, build, lib_path,
+    extract_window, sweep_box_from_field, sweep_box_window, reach_of,
 )

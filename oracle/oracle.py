@@ -42,7 +42,9 @@ def _lib():
         L.oracle_adjoint.argtypes = [i64, i64, i64, vp, i32, vp, vp, i32, vp, vp, i32,
                                      vp, vp, vp, vp]
         L.oracle_sweep_box.argtypes = [i64, i64, i64, vp, i32, vp, vp, i32, vp, vp, vp, vp]
-        for f in (L.oracle_sweep, L.oracle_transpose_step, L.oracle_adjoint, L.oracle_sweep_box):
+        L.oracle_sweep_box_win.argtypes = [i64, i64, i64, vp, i32, vp, vp, i32, vp, vp, vp, vp]
+        for f in (L.oracle_sweep, L.oracle_transpose_step, L.oracle_adjoint, L.oracle_sweep_box,
+                  L.oracle_sweep_box_win):
             f.restype = i32
         _LIB = L
     return _LIB
@@ -140,3 +142,73 @@ def sweep_box(u0, offsets, weights, T, box_lo, box_hi, periodic=(0, 0, 0)):
     if rc:
         raise RuntimeError(f"oracle_sweep_box failed ({rc})")
     return out[0] if np.asarray(u0).ndim == 2 else out
+
+
+def reach_of(offsets):
+    """Largest |offset| per axis (x, y, z)."""
+    off = np.asarray(offsets).reshape(-1, 3)
+    return tuple(int(np.abs(off[:, a]).max()) for a in (2, 1, 0))
+
+
+def extract_window(u, lo, hi, periodic):
+    """Values of field u (array (z, y, x), any float dtype, may be a view of a
+    huge array) at unreduced coordinates [lo, hi) per axis (x, y, z): wrapped
+    on periodic axes, zero outside the grid on Dirichlet axes.  FP64 result
+    shaped (z, y, x)."""
+    shape = u.shape if u.ndim == 3 else (1,) + u.shape
+    n = (shape[2], shape[1], shape[0])
+    idx, ok = [], []
+    for a in range(3):
+        c = np.arange(lo[a], hi[a])
+        if periodic[a]:
+            idx.append(np.mod(c, n[a]))
+            ok.append(np.ones(len(c), bool))
+        else:
+            inside = (c >= 0) & (c < n[a])
+            idx.append(np.clip(c, 0, n[a] - 1))
+            ok.append(inside)
+    u3 = u if u.ndim == 3 else u[None]
+    win = np.asarray(u3[np.ix_(idx[2], idx[1], idx[0])], dtype=np.float64)
+    mask = ok[2][:, None, None] & ok[1][None, :, None] & ok[0][None, None, :]
+    win[~mask] = 0.0
+    return np.ascontiguousarray(win)
+
+
+def sweep_box_from_field(u0, offsets, weights, T, box_lo, box_hi, periodic=(0, 0, 0)):
+    """u_T on the sub-box [box_lo, box_hi) of a field of any size (only the
+    box's dependency cone is read).  Returns (z, y, x) FP64."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    per = np.ascontiguousarray(np.asarray(periodic, dtype=np.int32).reshape(3))
+    shape = u0.shape if u0.ndim == 3 else (1,) + u0.shape
+    nx, ny, nz = shape[2], shape[1], shape[0]
+    reach = reach_of(off)
+    lo = np.asarray(box_lo, dtype=np.int64).reshape(3)
+    hi = np.asarray(box_hi, dtype=np.int64).reshape(3)
+    wlo = lo - T * np.asarray(reach)
+    whi = hi + T * np.asarray(reach)
+    win = extract_window(u0, wlo, whi, per)
+    return sweep_box_window(win, (nx, ny, nz), off, w, T, lo, hi, per)
+
+
+def sweep_box_window(win, grid, offsets, weights, T, box_lo, box_hi, periodic=(0, 0, 0)):
+    """u_T on [box_lo, box_hi) from a level-0 window covering the box dilated
+    by T*reach (see extract_window)."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+    per = np.ascontiguousarray(np.asarray(periodic, dtype=np.int32).reshape(3))
+    lo = np.ascontiguousarray(np.asarray(box_lo, dtype=np.int64).reshape(3))
+    hi = np.ascontiguousarray(np.asarray(box_hi, dtype=np.int64).reshape(3))
+    reach = reach_of(off)
+    ext = [int(hi[a] - lo[a] + 2 * T * reach[a]) for a in range(3)]
+    win = np.ascontiguousarray(win, dtype=np.float64)
+    if win.shape != (ext[2], ext[1], ext[0]):
+        raise ValueError(f"window shape {win.shape} != {(ext[2], ext[1], ext[0])}")
+    e = hi - lo
+    out = np.empty((e[2], e[1], e[0]))
+    nx, ny, nz = grid
+    rc = _lib().oracle_sweep_box_win(nx, ny, nz, _ptr(per), len(w), _ptr(off), _ptr(w), int(T),
+                                     _ptr(win), _ptr(lo), _ptr(hi), _ptr(out))
+    if rc:
+        raise RuntimeError(f"oracle_sweep_box_win failed ({rc})")
+    return out

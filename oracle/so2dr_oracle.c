@@ -181,10 +181,10 @@ int oracle_adjoint(int64_t nx, int64_t ny, int64_t nz, const int *periodic,
  * cell outside the grid is the zero boundary at every level.  Used to check
  * grids too large for the full sweep on a few sampled boxes.
  * out: (b1-b0) extents, x fastest. */
-int oracle_sweep_box(int64_t nx, int64_t ny, int64_t nz, const int *periodic,
-                     int npts, const int *off, const double *w, int T,
-                     const double *u0, const int64_t *b0, const int64_t *b1,
-                     double *out) {
+static int sweep_box_impl(int64_t nx, int64_t ny, int64_t nz, const int *periodic,
+                          int npts, const int *off, const double *w, int T,
+                          const double *u0, const double *win, const int64_t *b0,
+                          const int64_t *b1, double *out) {
   grid_t g;
   if (setup(&g, nx, ny, nz, periodic, npts, off, w) || T < 0) return -1;
   int64_t reach[3] = {0, 0, 0};
@@ -201,11 +201,13 @@ int oracle_sweep_box(int64_t nx, int64_t ny, int64_t nz, const int *periodic,
   const int64_t cap = e[0] * e[1] * e[2];
   double *a = malloc(sizeof(double) * cap), *b = malloc(sizeof(double) * cap);
   if (!a || !b) { free(a); free(b); return -2; }
-  /* level 0 over the full window */
+  /* level 0 over the full window: from u0 under the boundary rule, or, when
+   * u0 is NULL, from the caller's window (already extended, same extents) */
   for (int64_t k = 0; k < e[2]; ++k)
     for (int64_t j = 0; j < e[1]; ++j)
       for (int64_t i = 0; i < e[0]; ++i)
-        a[(k * e[1] + j) * e[0] + i] = ext(&g, u0, lo[0] + i, lo[1] + j, lo[2] + k);
+        a[(k * e[1] + j) * e[0] + i] =
+            u0 ? ext(&g, u0, lo[0] + i, lo[1] + j, lo[2] + k) : win[(k * e[1] + j) * e[0] + i];
   int64_t pe[3] = {e[0], e[1], e[2]}, plo[3] = {lo[0], lo[1], lo[2]};
   for (int t = 1; t <= T; ++t) {
     int64_t ce[3], clo[3];
@@ -234,4 +236,23 @@ int oracle_sweep_box(int64_t nx, int64_t ny, int64_t nz, const int *periodic,
   memcpy(out, a, sizeof(double) * pe[0] * pe[1] * pe[2]);
   free(a); free(b);
   return 0;
+}
+
+int oracle_sweep_box(int64_t nx, int64_t ny, int64_t nz, const int *periodic,
+                     int npts, const int *off, const double *w, int T,
+                     const double *u0, const int64_t *b0, const int64_t *b1,
+                     double *out) {
+  if (!u0) return -1;
+  return sweep_box_impl(nx, ny, nz, periodic, npts, off, w, T, u0, NULL, b0, b1, out);
+}
+
+/* As oracle_sweep_box, with level 0 given directly as the window: the box
+ * dilated by T*reach per axis, x fastest, in unreduced coordinates (values
+ * outside the grid already wrapped or zeroed by the boundary rule). */
+int oracle_sweep_box_win(int64_t nx, int64_t ny, int64_t nz, const int *periodic,
+                         int npts, const int *off, const double *w, int T,
+                         const double *win, const int64_t *b0, const int64_t *b1,
+                         double *out) {
+  if (!win) return -1;
+  return sweep_box_impl(nx, ny, nz, periodic, npts, off, w, T, NULL, win, b0, b1, out);
 }

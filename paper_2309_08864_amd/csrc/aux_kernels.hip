@@ -1,3 +1,149 @@
-// aux_kernels.hip -- small device helpers shared by the executor (reserved
-// for the adjoint's FP64 reductions).
-#include <hip/hip_runtime.h>
+// aux_kernels.hip -- FP64 reductions of the adjoint (loss and weight
+// gradients).  Not in the paper: the gradient of L = 1/2 ||u_T - y||^2 with
+// respect to the weights is sum_t sum_x lambda_{t+1}(x) u_t(x + o_k), and the
+// loss itself; both are accumulated in FP64 on the GPU.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "aux.hpp"
+#include "../../include/so2dr.h"
+
+namespace so2dr {
+
+constexpr int kRedThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) { return (double)v; }
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void loss_kernel(T *lam_u, const T *y, int64_t n, double *partials) {
+  __shared__ double red[kRedThreads];
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double d = to_d(lam_u[i]) - to_d(y[i]);   // exact for FP32 inputs
+    lam_u[i] = (T)d;                                 // one rounding, as u - y in T
+    s += 0.5 * d * d;
+  }
+  const double b = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+// acc[k] += sum_b partials[b * np + k], one lane per k, blocks in order.
+__global__ void reduce_partials(const double *partials, int nb, int np, double *acc) {
+  const int k = threadIdx.x;
+  if (k >= np) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partials[(int64_t)b * np + k];
+  acc[k] += s;
+}
+
+template <typename T, int NP>
+__global__ __launch_bounds__(256) void wgrad_kernel(const T *lam, const T *u, int64_t buf_z0, int nx,
+                                                    int ny, int per_x, int per_y, int64_t n_axis,
+                                                    int64_t z0, int64_t z1, RedOffsets o,
+                                                    double *partials) {
+  __shared__ double red[kRedThreads];
+  double acc[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t n = (z1 - z0) * plane;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t z = z0 + i / plane;
+    const int64_t rem = i % plane;
+    const int y = (int)(rem / nx), x = (int)(rem % nx);
+    const double l = to_d(lam[(z - buf_z0) * plane + rem]);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int64_t zz = z + o.dz[k];
+      int yy = y + o.dy[k], xx = x + o.dx[k];
+      if (zz < 0 || zz >= n_axis) continue;
+      if (xx < 0 || xx >= nx) {
+        if (!per_x) continue;
+        xx = xx < 0 ? xx + nx : xx - nx;
+      }
+      if (yy < 0 || yy >= ny) {
+        if (!per_y) continue;
+        yy = yy < 0 ? yy + ny : yy - ny;
+      }
+      acc[k] += l * to_d(u[(zz - buf_z0) * plane + (int64_t)yy * nx + xx]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const double b = block_sum(acc[k], red);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * NP + k] = b;
+  }
+}
+
+template <typename T>
+static int loss_t(void *lam_u, const void *y, int64_t n, double *partials, double *acc, hipStream_t s) {
+  hipLaunchKernelGGL(loss_kernel<T>, dim3(kRedWgs), dim3(kRedThreads), 0, s, static_cast<T *>(lam_u),
+                     static_cast<const T *>(y), n, partials);
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(64), 0, s, partials, kRedWgs, 1, acc);
+  return hipGetLastError() == hipSuccess ? 0 : SO2DR_E_HIP;
+}
+
+int launch_loss(int dtype, void *lam_u, const void *y, int64_t n, double *partials, double *acc,
+                hipStream_t s) {
+  if (n <= 0) return 0;
+  switch (dtype) {
+    case SO2DR_F32: return loss_t<float>(lam_u, y, n, partials, acc, s);
+    case SO2DR_F64: return loss_t<double>(lam_u, y, n, partials, acc, s);
+    default: return SO2DR_E_UNSUPPORTED;
+  }
+}
+
+template <typename T, int NP>
+static int wgrad_np(const void *lam, const void *u, int64_t buf_z0, int nx, int ny, int per_x, int per_y,
+                    int64_t n_axis, int64_t z0, int64_t z1, const RedOffsets &o, double *partials,
+                    double *acc, hipStream_t s) {
+  hipLaunchKernelGGL((wgrad_kernel<T, NP>), dim3(kRedWgs), dim3(kRedThreads), 0, s,
+                     static_cast<const T *>(lam), static_cast<const T *>(u), buf_z0, nx, ny, per_x,
+                     per_y, n_axis, z0, z1, o, partials);
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(128), 0, s, partials, kRedWgs, NP, acc);
+  return hipGetLastError() == hipSuccess ? 0 : SO2DR_E_HIP;
+}
+
+template <typename T>
+static int wgrad_t(const void *lam, const void *u, int64_t buf_z0, int nx, int ny, int per_x, int per_y,
+                   int64_t n_axis, int64_t z0, int64_t z1, const RedOffsets &o, int npts,
+                   double *partials, double *acc, hipStream_t s) {
+#define SO2DR_NP(N) \
+  case N: return wgrad_np<T, N>(lam, u, buf_z0, nx, ny, per_x, per_y, n_axis, z0, z1, o, partials, acc, s);
+  switch (npts) {
+    SO2DR_NP(5) SO2DR_NP(7) SO2DR_NP(9) SO2DR_NP(13) SO2DR_NP(25) SO2DR_NP(27) SO2DR_NP(49) SO2DR_NP(81)
+    default: return SO2DR_E_UNSUPPORTED;
+  }
+#undef SO2DR_NP
+}
+
+int launch_wgrad(int dtype, const void *lam, const void *u, int64_t buf_z0, int nx, int ny, int per_x,
+                 int per_y, int64_t n_axis, int64_t z0, int64_t z1, const RedOffsets &offs, int npts,
+                 double *partials, double *acc, hipStream_t s) {
+  if (z1 <= z0) return 0;
+  switch (dtype) {
+    case SO2DR_F32:
+      return wgrad_t<float>(lam, u, buf_z0, nx, ny, per_x, per_y, n_axis, z0, z1, offs, npts, partials, acc, s);
+    case SO2DR_F64:
+      return wgrad_t<double>(lam, u, buf_z0, nx, ny, per_x, per_y, n_axis, z0, z1, offs, npts, partials, acc, s);
+    default:
+      return SO2DR_E_UNSUPPORTED;
+  }
+}
+
+}  // namespace so2dr

@@ -87,7 +87,7 @@ int so2dr_plan_get_info(const so2dr_plan *plan, so2dr_plan_info *info) {
   info->slot_planes = (int)P.slot_planes;
   info->max_k_on = P.max_k_on;
   info->workspace_bytes = P.workspace;
-  info->slot_bytes = 2 * P.buf_bytes;
+  info->slot_bytes = (size_t)P.bufs_per_slot * P.buf_bytes;
   info->rs_bytes = P.rs_bytes;
   info->scratch_bytes = P.scratch_bytes;
   int64_t computed = 0;

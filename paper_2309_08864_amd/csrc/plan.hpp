@@ -27,8 +27,8 @@ struct Plan {
   int64_t slot_planes = 0;
   size_t buf_bytes = 0;            // one ping-pong buffer (256-aligned)
   size_t rs_bytes = 0, scratch_bytes = 0, workspace = 0, budget = 0;
-  size_t adj_bytes = 0;            // extra space reserved for the adjoint
   bool adjoint = false;
+  int bufs_per_slot = 2;           // 2 ping-pong buffers; 5 when the adjoint is planned
   // ---- bound state
   char *arena = nullptr;
   size_t arena_bytes = 0;
@@ -41,10 +41,13 @@ struct Plan {
 
   size_t plane_bytes() const { return (size_t)plane * elem; }
   char *slot_buf(int slot, int which) const {
-    return arena + ((size_t)slot * 2 + (size_t)which) * buf_bytes;
+    return arena + ((size_t)slot * bufs_per_slot + (size_t)which) * buf_bytes;
   }
-  char *rs_pool() const { return arena + (size_t)n_slots * 2 * buf_bytes; }
-  char *scratch() const { return rs_pool() + rs_bytes; }
+  char *rs_pool(int which = 0) const {
+    return arena + (size_t)n_slots * bufs_per_slot * buf_bytes + (size_t)which * rs_bytes;
+  }
+  int n_rs() const { return adjoint ? 2 : 1; }
+  char *scratch() const { return rs_pool(0) + (size_t)n_rs() * rs_bytes; }
 };
 
 // Geometry of round `t` for a run of `steps` steps.

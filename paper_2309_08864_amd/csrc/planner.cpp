@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "aux.hpp"
 #include "depths.hpp"
 #include "plan.hpp"
 
@@ -164,11 +165,13 @@ static size_t plan_bytes(Plan &P, int d, int slots) {
   P.buf_bytes = align256((size_t)sp * P.plane_bytes());
   P.rs_bytes = align256((size_t)halo * P.plane_bytes());
   P.n_slots = slots;
-  // adjoint: two more field buffers per slot (the lambda pair) plus FP64
-  // partial-sum scratch for the loss and weight gradients
-  P.adj_bytes = P.adjoint ? (size_t)slots * 2 * P.buf_bytes + P.rs_bytes : 0;
-  P.scratch_bytes = P.adjoint ? align256(sizeof(double) * 4096 * 96) : 0;
-  return (size_t)slots * 2 * P.buf_bytes + P.rs_bytes + P.adj_bytes + P.scratch_bytes;
+  // adjoint: per slot the round-start state, a recompute pair and the
+  // adjoint pair; a second region-sharing buffer for the adjoint field; FP64
+  // partial sums for the loss and weight-gradient reductions
+  P.bufs_per_slot = P.adjoint ? 5 : 2;
+  P.scratch_bytes = P.adjoint ? align256(sizeof(double) * (kRedWgs * kMaxRedPts + 256)) : 0;
+  return (size_t)slots * P.bufs_per_slot * P.buf_bytes + (size_t)P.n_rs() * P.rs_bytes +
+         P.scratch_bytes;
 }
 
 static bool chunks_ok(const Plan &P, int d) {
@@ -277,7 +280,8 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     if (!chosen) { set_error("no chunk count fits the device budget"); return SO2DR_E_BUDGET; }
     plan_bytes(*P, chosen, chosen_slots);
   }
-  P->workspace = (size_t)P->n_slots * 2 * P->buf_bytes + P->rs_bytes + P->adj_bytes + P->scratch_bytes;
+  P->workspace = (size_t)P->n_slots * P->bufs_per_slot * P->buf_bytes + (size_t)P->n_rs() * P->rs_bytes +
+                 P->scratch_bytes;
   return SO2DR_OK;
 }
 

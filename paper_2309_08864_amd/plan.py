@@ -40,6 +40,8 @@ class Plan:
                  adjoint=False):
         self.storage = storage
         self.shape3 = (nz, ny, nx)
+        self._T = T
+        self._nw = len(weights)
         self._w = (ctypes.c_double * len(weights))(*[float(x) for x in weights])
         d = _lib.Desc()
         d.ndim, d.nx, d.ny, d.nz = ndim, nx, ny, nz
@@ -125,3 +127,40 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def adjoint_buffers_needed(T, tb_depth, ckpt_every):
+    """Pinned host fields so2dr_adjoint_run needs: one per segment start after
+    the first, plus the round starts inside one segment."""
+    if T <= 0:
+        return 0
+    c = min(ckpt_every, T)
+    nseg = -(-T // c)
+    return max(0, nseg - 1) + max(0, -(-c // tb_depth) - 1)
+
+
+def _adjoint(self, u0, target, ckpt_every, ckpt=None, grad_u0=None):
+    """Gradient of L = 1/2 ||u_T - target||^2.  u0, target: pinned host
+    tensors of the storage type (F32 or F64).  Returns (loss, grad_u0,
+    grad_w, stats); grad_w is an FP64 numpy array in weight order."""
+    import torch
+    info = self.info()
+    self._check_host(u0)
+    self._check_host(target)
+    need = adjoint_buffers_needed(self._T, info["tb_depth"], ckpt_every)
+    if ckpt is None:
+        ckpt = [torch.empty(u0.shape, dtype=u0.dtype, pin_memory=True) for _ in range(need)]
+    if grad_u0 is None:
+        grad_u0 = torch.empty(u0.shape, dtype=u0.dtype, pin_memory=True)
+    arr = (ctypes.c_void_p * max(1, len(ckpt)))(*[t.data_ptr() for t in ckpt])
+    gw = (ctypes.c_double * self._nw)()
+    loss = ctypes.c_double()
+    st = _lib.Stats()
+    check(lib().so2dr_adjoint_run(self._h, ctypes.c_void_p(u0.data_ptr()),
+                                  ctypes.c_void_p(target.data_ptr()),
+                                  ctypes.c_void_p(grad_u0.data_ptr()), gw, ctypes.byref(loss),
+                                  int(ckpt_every), arr, len(ckpt), ctypes.byref(st)))
+    return loss.value, grad_u0, np.array(gw[:]), st.as_dict()
+
+
+Plan.adjoint = _adjoint

@@ -308,6 +308,28 @@ def test_p6_subbox_matches_full(ndim, shape, r, bc):
         assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("ndim,shape,r", [(3, "star", 2), (3, "box", 1), (2, "box", 3)])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0)])
+def test_p6_window_sweep_matches_full(ndim, shape, r, bc):
+    """The window form (level 0 extracted with the boundary rule, used for
+    grids too large to convert whole) equals the full sweep, on float32
+    input as the large workloads store it."""
+    rng = np.random.default_rng(750 + r)
+    offs = stencil_offsets(ndim, shape, r)
+    w = rng.uniform(0, 1, len(offs))
+    shp = (23, 19) if ndim == 2 else (13, 12, 11)
+    per = _bc_for(ndim, bc)
+    u0 = rng.random(shp).astype(np.float32)
+    T = 3
+    full = _as3(sweep(u0.astype(np.float64), offs, w, T, per))
+    ns = full.shape[::-1]
+    for _ in range(3):
+        lo = [int(rng.integers(0, n)) for n in ns]
+        hi = [min(n, l + int(rng.integers(1, 4))) for l, n in zip(lo, ns)]
+        got = oracle.sweep_box_from_field(u0, offs, w, T, lo, hi, per)
+        assert np.array_equal(got, full[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])
+
+
 @pytest.mark.parametrize("shape", ["star", "box"])
 def test_p6_impulse_support(shape):
     offs = stencil_offsets(3, shape, 1)
