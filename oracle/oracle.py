@@ -155,7 +155,7 @@ def extract_window(u, lo, hi, periodic):
     huge array) at unreduced coordinates [lo, hi) per axis (x, y, z): wrapped
     on periodic axes, zero outside the grid on Dirichlet axes.  FP64 result
     shaped (z, y, x)."""
-    shape = u.shape if u.ndim == 3 else (1,) + u.shape
+    shape = tuple(u.shape) if u.ndim == 3 else (1,) + tuple(u.shape)
     n = (shape[2], shape[1], shape[0])
     idx, ok = [], []
     for a in range(3):
@@ -168,7 +168,14 @@ def extract_window(u, lo, hi, periodic):
             idx.append(np.clip(c, 0, n[a] - 1))
             ok.append(inside)
     u3 = u if u.ndim == 3 else u[None]
-    win = np.asarray(u3[np.ix_(idx[2], idx[1], idx[0])], dtype=np.float64)
+    if hasattr(u3, "index_select"):   # a torch tensor (e.g. bfloat16 storage)
+        import torch
+        g = u3.index_select(0, torch.from_numpy(idx[2]))
+        g = g.index_select(1, torch.from_numpy(idx[1]))
+        g = g.index_select(2, torch.from_numpy(idx[0]))
+        win = g.double().numpy()
+    else:
+        win = np.asarray(u3[np.ix_(idx[2], idx[1], idx[0])], dtype=np.float64)
     mask = ok[2][:, None, None] & ok[1][None, :, None] & ok[0][None, None, :]
     win[~mask] = 0.0
     return np.ascontiguousarray(win)
@@ -180,7 +187,7 @@ def sweep_box_from_field(u0, offsets, weights, T, box_lo, box_hi, periodic=(0, 0
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
     w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
     per = np.ascontiguousarray(np.asarray(periodic, dtype=np.int32).reshape(3))
-    shape = u0.shape if u0.ndim == 3 else (1,) + u0.shape
+    shape = tuple(u0.shape) if u0.ndim == 3 else (1,) + tuple(u0.shape)
     nx, ny, nz = shape[2], shape[1], shape[0]
     reach = reach_of(off)
     lo = np.asarray(box_lo, dtype=np.int64).reshape(3)

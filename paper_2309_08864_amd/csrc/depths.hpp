@@ -8,7 +8,7 @@ namespace so2dr {
 // rows: so2dr_dtype F32, F64, BF16, F16; columns: StencilId
 constexpr int kMaxDepth[4][ST_COUNT] = {
     /* F32  */ {8, 8, 4, 4, 4, 4, 2, 4},
-    /* F64  */ {4, 0, 0, 0, 0, 2, 0, 2},
+    /* F64  */ {4, 4, 2, 2, 2, 2, 2, 2},
     /* BF16 */ {8, 0, 0, 0, 0, 4, 2, 4},
     /* F16  */ {8, 0, 0, 0, 0, 4, 2, 4},
 };

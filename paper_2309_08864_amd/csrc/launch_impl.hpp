@@ -5,7 +5,24 @@
 #include <string>
 
 #include "launch.hpp"
+#include "star_kernel.hpp"
 #include "tb_kernel.hpp"
+
+#ifndef SO2DR_STAR_KERNEL
+#define SO2DR_STAR_KERNEL 1
+#endif
+#ifndef SO2DR_STAR_NW
+#define SO2DR_STAR_NW 8
+#endif
+#ifndef SO2DR_STAR_M
+#define SO2DR_STAR_M 2
+#endif
+#ifndef SO2DR_STAR_VX
+#define SO2DR_STAR_VX 4
+#endif
+#ifndef SO2DR_STAR_HB
+#define SO2DR_STAR_HB 2
+#endif
 
 namespace so2dr {
 
@@ -19,6 +36,14 @@ namespace so2dr {
 #endif
 constexpr int64_t kTargetWgs = SO2DR_TARGET_WGS;
 constexpr int64_t kMinSegPlanes = SO2DR_MIN_SEG;
+
+// Segmenting of the cut axis shared by both kernel families.
+inline void plan_segments(int64_t span, int64_t tiles, int64_t *zseg, int *nseg) {
+  int64_t n = std::max<int64_t>(1, (kTargetWgs + tiles - 1) / tiles);
+  n = std::min<int64_t>(n, std::max<int64_t>(1, span / kMinSegPlanes));
+  *zseg = (span + n - 1) / n;
+  *nseg = (int)((span + *zseg - 1) / *zseg);
+}
 
 template <typename T, int NDIM, bool BOX, int R, int KL>
 int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
@@ -48,12 +73,8 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   a.nty = NDIM == 2 ? 1 : (int)((p.ny + G::OY - 1) / G::OY);
   const int64_t span = p.out_hi - p.out_lo;
   if (span <= 0) return 0;
-  const int64_t tiles = (int64_t)a.ntx * a.nty;
-  int64_t nseg = std::max<int64_t>(1, (kTargetWgs + tiles - 1) / tiles);
-  nseg = std::min<int64_t>(nseg, std::max<int64_t>(1, span / kMinSegPlanes));
-  a.zseg = (span + nseg - 1) / nseg;
-  a.nseg = (int)((span + a.zseg - 1) / a.zseg);
-  const int64_t nwg = tiles * a.nseg;
+  plan_segments(span, (int64_t)a.ntx * a.nty, &a.zseg, &a.nseg);
+  const int64_t nwg = (int64_t)a.ntx * a.nty * a.nseg;
   if (nwg > 0x7fffffff) {
     if (msg) *msg = "grid too large for one launch";
     return -1;
@@ -81,18 +102,76 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   return 0;
 }
 
+template <typename T, int R, int KL>
+int launch_star_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
+  using A = typename Store<T>::A;
+  constexpr int NW = SO2DR_STAR_NW, M = SO2DR_STAR_M, VX = SO2DR_STAR_VX, HB = SO2DR_STAR_HB;
+  using G = StarTile<R, KL, NW, M, VX>;
+  using S = Stencil<3, false, R>;
+  if (p.npts != S::npts()) {
+    if (msg) *msg = "weight count does not match the stencil";
+    return -1;
+  }
+  TbArgs<A> a{};
+  a.in = p.in;
+  a.out = p.out;
+  a.buf_z0 = p.buf_z0;
+  a.plane = p.plane;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.per_x = p.per_x;
+  a.per_y = p.per_y;
+  a.n_axis = p.n_axis;
+  a.in_lo = p.in_lo;
+  a.in_hi = p.in_hi;
+  a.out_lo = p.out_lo;
+  a.out_hi = p.out_hi;
+  for (int i = 0; i < S::npts(); ++i) a.w.w[i] = (A)p.weights[i];
+  a.ntx = (int)((p.nx + G::OX - 1) / G::OX);
+  a.nty = (int)((p.ny + G::OY - 1) / G::OY);
+  const int64_t span = p.out_hi - p.out_lo;
+  if (span <= 0) return 0;
+  plan_segments(span, (int64_t)a.ntx * a.nty, &a.zseg, &a.nseg);
+  const int64_t nwg = (int64_t)a.ntx * a.nty * a.nseg;
+  if (nwg > 0x7fffffff) {
+    if (msg) *msg = "grid too large for one launch";
+    return -1;
+  }
+  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  hipLaunchKernelGGL((star3d_kernel<T, R, KL, NW, M, VX, HB>), dim3((unsigned)grid), dim3(NW * 64), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (msg) *msg = std::string("kernel launch: ") + hipGetErrorString(e);
+    return -5;
+  }
+  return 0;
+}
+
+// 3D star stencils go to the register-column kernel, everything else to the
+// LDS-plane kernel; both compute the same bits.
+template <typename T, int NDIM, bool BOX, int R, int KL>
+int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
+  constexpr size_t star_lds =
+      sizeof(typename Store<T>::A) * KL * SO2DR_STAR_HB * SO2DR_STAR_NW * 2 * R * 64 * SO2DR_STAR_VX;
+  if constexpr (NDIM == 3 && !BOX && SO2DR_STAR_KERNEL && (KL * R * 2 < SO2DR_STAR_NW * SO2DR_STAR_M) &&
+                star_lds <= 65536)
+    return launch_star_one<T, R, KL>(p, s, msg);
+  else
+    return launch_one<T, NDIM, BOX, R, KL>(p, s, msg);
+}
+
 // Expand one stencil's depths 1..MAXKL into a switch on p.kl.
 template <typename T, int NDIM, bool BOX, int R, int MAXKL>
 int launch_depth(const LaunchParams &p, hipStream_t s, std::string *msg) {
   switch (p.kl) {
-    case 1: return launch_one<T, NDIM, BOX, R, 1>(p, s, msg);
-    case 2: if constexpr (MAXKL >= 2) return launch_one<T, NDIM, BOX, R, 2>(p, s, msg); else break;
-    case 3: if constexpr (MAXKL >= 3) return launch_one<T, NDIM, BOX, R, 3>(p, s, msg); else break;
-    case 4: if constexpr (MAXKL >= 4) return launch_one<T, NDIM, BOX, R, 4>(p, s, msg); else break;
-    case 5: if constexpr (MAXKL >= 5) return launch_one<T, NDIM, BOX, R, 5>(p, s, msg); else break;
-    case 6: if constexpr (MAXKL >= 6) return launch_one<T, NDIM, BOX, R, 6>(p, s, msg); else break;
-    case 7: if constexpr (MAXKL >= 7) return launch_one<T, NDIM, BOX, R, 7>(p, s, msg); else break;
-    case 8: if constexpr (MAXKL >= 8) return launch_one<T, NDIM, BOX, R, 8>(p, s, msg); else break;
+    case 1: return launch_any<T, NDIM, BOX, R, 1>(p, s, msg);
+    case 2: if constexpr (MAXKL >= 2) return launch_any<T, NDIM, BOX, R, 2>(p, s, msg); else break;
+    case 3: if constexpr (MAXKL >= 3) return launch_any<T, NDIM, BOX, R, 3>(p, s, msg); else break;
+    case 4: if constexpr (MAXKL >= 4) return launch_any<T, NDIM, BOX, R, 4>(p, s, msg); else break;
+    case 5: if constexpr (MAXKL >= 5) return launch_any<T, NDIM, BOX, R, 5>(p, s, msg); else break;
+    case 6: if constexpr (MAXKL >= 6) return launch_any<T, NDIM, BOX, R, 6>(p, s, msg); else break;
+    case 7: if constexpr (MAXKL >= 7) return launch_any<T, NDIM, BOX, R, 7>(p, s, msg); else break;
+    case 8: if constexpr (MAXKL >= 8) return launch_any<T, NDIM, BOX, R, 8>(p, s, msg); else break;
     default: break;
   }
   if (msg) *msg = "fused depth not built for this stencil";

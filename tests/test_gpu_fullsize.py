@@ -1,0 +1,262 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark uses: sampled output boxes against the FP64 oracle's light-cone
+sub-box sweep (it reads only each box's dependency cone of u0), bit-for-bit
+in-core vs out-of-core where two fields fit in HBM, and for the adjoint,
+identities that hold at any size.
+
+Large pinned host fields: 2D 5-point 1024^2; 3D 7-point and 27-point
+2048x1024x1024 (8 GiB per FP32 field); 13-point 2048^3 (32 GiB FP32);
+adjoint 1024^3 (4 GiB per field, 8 checkpoints)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from helpers import pinned_copy, rel_l2
+from paper_2309_08864_amd import Plan, So2drError, stencil_offsets
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+WL = workloads.CONFIGS
+
+
+def _log(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def _weights(wl, offs):
+    tag = wl.weights.split(":")
+    if tag[0] == "const":
+        w = workloads.const_weights(offs, float(tag[1]))
+    elif tag[0] == "centre_arm":
+        w = workloads.centre_arm_weights(offs, float(tag[1]), [float(x) for x in tag[2:]])
+    else:
+        w = workloads.random_box_weights(offs, wl.seed)
+    return w
+
+
+def _pinned(shape, dtype):
+    return torch.empty(shape, dtype=dtype, pin_memory=True)
+
+
+def _sample_boxes(nx, ny, nz, n_chunks, rng, size=3, extra=4):
+    """Boxes at the corners, across chunk boundaries and at random places."""
+    boxes = []
+    corners = [(0, 0, 0), (nx - size, ny - size, nz - size), (0, ny - size, nz // 2),
+               (nx - size, 0, 0)]
+    for c in corners:
+        boxes.append(c)
+    for i in range(1, min(n_chunks, 3)):
+        z = nz * i // n_chunks - size // 2
+        boxes.append((int(rng.integers(0, nx - size)), int(rng.integers(0, ny - size)), z))
+    for _ in range(extra):
+        boxes.append(tuple(int(rng.integers(0, n - size + 1)) for n in (nx, ny, nz)))
+    return [(b, tuple(v + size for v in b)) for b in boxes]
+
+
+def _check_boxes(u0_np, got_np, offs, w, T, per, boxes, tol, tag):
+    worst = 0.0
+    for lo, hi in boxes:
+        ref = oracle.sweep_box_from_field(u0_np, offs, w, T, lo, hi, per)
+        g = got_np[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].astype(np.float64)
+        e = rel_l2(g, ref)
+        worst = max(worst, e)
+        assert e <= tol, f"{tag}: box {lo}-{hi} rel L2 {e:.3e}"
+    _log(f"{tag}: {len(boxes)} boxes, worst rel L2 vs FP64 oracle {worst:.3e}")
+    return worst
+
+
+def test_c1_2d5pt_full():
+    """2D 5-point, 1024^2, 4 row chunks, TB depth 4, 4 MiB budget, FP32; FP64
+    with the same chunks needs 4.19 MiB with two ping-pong buffers, so the
+    planner refuses it under 4 MiB and it runs with 8 chunks instead."""
+    wl = WL["c1_2d5pt"]
+    offs = stencil_offsets(2, "star", 1)
+    w = _weights(wl, offs)
+    u64 = workloads.uniform((wl.ny, wl.nx), seed=wl.seed)
+    base = dict(ndim=2, nx=wl.nx, ny=wl.ny, nz=1, shape="star", radius=1, T=wl.T,
+                tb_depth=wl.tb_depth, budget=wl.budget)
+    # FP32, 4 chunks, 4 MiB
+    w32 = workloads.fp32_rounded(w)
+    u32 = torch.from_numpy(u64.astype(np.float32))
+    p = Plan(weights=list(w32), n_chunks=4, **base).bind()
+    assert p.info()["workspace_bytes"] <= 4 << 20 and p.info()["n_chunks"] == 4
+    h = pinned_copy(u32)
+    p.run(h)
+    p.close()
+    ref = oracle.sweep(u32.double().numpy(), offs, w32, wl.T)
+    e32 = rel_l2(h.double().numpy(), ref)
+    _log(f"c1 FP32 rel L2 {e32:.3e}")
+    assert e32 <= 1e-5
+    # in-core bitwise
+    pin = Plan(weights=list(w32), n_chunks=1, **dict(base, tb_depth=wl.T, budget=64 << 20)).bind()
+    hi = pinned_copy(u32)
+    pin.run(hi)
+    pin.close()
+    assert torch.equal(hi, h)
+    # FP64
+    with pytest.raises(So2drError, match="E_BUDGET"):
+        Plan(weights=list(w), n_chunks=4, storage="f64", **base)
+    p = Plan(weights=list(w), n_chunks=8, storage="f64", **base).bind()
+    assert p.info()["workspace_bytes"] <= 4 << 20
+    h = pinned_copy(torch.from_numpy(u64))
+    p.run(h)
+    p.close()
+    e64 = rel_l2(h.numpy(), oracle.sweep(u64, offs, w, wl.T))
+    _log(f"c1 FP64 (8 chunks) rel L2 {e64:.3e}")
+    assert e64 <= 1e-12
+
+
+def _full_3d(name, k_on=0):
+    wl = WL[name]
+    offs = stencil_offsets(3, wl.shape, wl.radius)
+    w = workloads.fp32_rounded(_weights(wl, offs))
+    shp = (wl.nz, wl.ny, wl.nx)
+    h_in = _pinned(shp, torch.float32)
+    t0 = time.time()
+    if wl.init == "uniform":
+        workloads.uniform_into(h_in.numpy(), wl.seed)
+    elif wl.init == "fourier":
+        workloads.fourier_modes_into(h_in.numpy(), wl.seed)
+    _log(f"{name}: input ready in {time.time() - t0:.1f} s")
+    kw = dict(ndim=3, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
+              weights=list(w), T=wl.T, bc=wl.periodic)
+    p = Plan(tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, k_on=k_on, budget=wl.budget, **kw).bind()
+    info = p.info()
+    assert info["workspace_bytes"] <= wl.budget
+    h_out = _pinned(shp, torch.float32)
+    st = p.run_steps(h_in, h_out, wl.T)
+    p.close()
+    _log(f"{name}: out-of-core {st['wall_ms']:.0f} ms, {info['n_chunks']} chunks, "
+         f"{info['n_slots']} slots, k_on {info['k_on']}")
+    rng = np.random.default_rng(7)
+    boxes = _sample_boxes(wl.nx, wl.ny, wl.nz, info["n_chunks"], rng)
+    _check_boxes(h_in.numpy(), h_out.numpy(), offs, w, wl.T, wl.periodic, boxes, 1e-5, name)
+    # bit-for-bit against the in-core run (two 8 GiB fields fit in HBM)
+    pin = Plan(tb_depth=wl.T, n_chunks=1, budget=24 << 30, **kw).bind()
+    h_ic = _pinned(shp, torch.float32)
+    pin.run_steps(h_in, h_ic, wl.T)
+    pin.close()
+    assert torch.equal(h_ic, h_out), f"{name}: out-of-core differs from in-core"
+    _log(f"{name}: out-of-core == in-core bit for bit")
+
+
+def test_c2_3d7pt_full():
+    _full_3d("c2_3d7pt")
+
+
+def test_c3_3d27pt_full():
+    _full_3d("c3_3d27pt")
+
+
+def test_c4_3d13pt_full_precision():
+    """2048^3 13-point star, FP32 then BF16 then FP16 storage, in place.  The
+    FP32 field (FP64 recipe rounded once) is the reference input; the BF16 /
+    FP16 inputs are its roundings.  Each storage type is checked on sampled
+    boxes against the oracle run from its own input (arithmetic error, must
+    stay under the per-step rounding bound) and reported against the FP32
+    input's oracle result (total error)."""
+    wl = WL["c4_3d13pt"]
+    offs = stencil_offsets(3, "star", 2)
+    w = workloads.fp32_rounded(_weights(wl, offs))
+    shp = (wl.nz, wl.ny, wl.nx)
+    h32 = _pinned(shp, torch.float32)
+    t0 = time.time()
+    workloads.gaussian_bump_into(h32.numpy(), wl.seed)
+    _log(f"c4: input ready in {time.time() - t0:.1f} s")
+    max_u0 = float(h32.abs().max())
+    rng = np.random.default_rng(11)
+    boxes = _sample_boxes(wl.nx, wl.ny, wl.nz, 32, rng, size=2, extra=3)
+    refs32 = [oracle.sweep_box_from_field(h32.numpy(), offs, w, wl.T, lo, hi) for lo, hi in boxes]
+    # reduced-storage inputs and their own oracle references, before h32 is overwritten
+    lows = {}
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        t = _pinned(shp, dt)
+        for z0 in range(0, wl.nz, 64):
+            t[z0:z0 + 64].copy_(h32[z0:z0 + 64])
+        lows[name] = t
+    refs_low = {name: [oracle.sweep_box_from_field(t, offs, w, wl.T, lo, hi) for lo, hi in boxes]
+                for name, t in lows.items()}
+    base = dict(ndim=3, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape="star", radius=2, weights=list(w),
+                T=wl.T, tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, budget=wl.budget)
+    for name, t in (("f32", h32), ("bf16", lows["bf16"]), ("f16", lows["f16"])):
+        p = Plan(storage=name, **base).bind()
+        st = p.run(t)
+        p.close()
+        _log(f"c4 {name}: {st['wall_ms']:.0f} ms")
+        worst_arith, worst_total = 0.0, 0.0
+        unit = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}[name]
+        for (lo, hi), r32, k in zip(boxes, refs32, range(len(boxes))):
+            g = t[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].double().numpy()
+            e_tot = rel_l2(g, r32)
+            worst_total = max(worst_total, e_tot)
+            ref_own = r32 if name == "f32" else refs_low[name][k]
+            err = np.abs(g - ref_own).max()
+            # weights >= 0 summing to 1: ||A||_inf <= 1, so the error is at most
+            # the per-step roundings summed: T (u_storage + P 2^-24) max|u0|
+            bound = wl.T * (unit + 13 * 2.0 ** -24) * max_u0
+            worst_arith = max(worst_arith, err)
+            assert err <= bound, f"c4 {name}: box {lo} max err {err:.3e} > bound {bound:.3e}"
+        _log(f"c4 {name}: worst total rel L2 vs FP64 oracle (FP32 input) {worst_total:.3e}; "
+             f"worst arithmetic max err {worst_arith:.3e}")
+        if name == "f32":
+            assert worst_total <= 1e-5
+    del lows
+
+
+def test_c5_adjoint_full():
+    """Adjoint of the 7-point sweep at 1024^3, T = 128, checkpoints every 16
+    steps, 2 GiB budget.  Checks: the loss against 1/2 ||u_T - y||^2 from a
+    forward run; the exact identities <grad_u0, u0> = <u_T - y, u_T> (u_T is
+    linear in u0) and sum_k w_k dL/dw_k = T <u_T - y, u_T> (u_T is
+    homogeneous of degree T in w); and dL/du0 on a sampled box against the
+    FP64 oracle's light-cone reverse sweep."""
+    wl = WL["c5_adjoint"]
+    offs = stencil_offsets(3, "star", 1)
+    w = workloads.fp32_rounded(_weights(wl, offs))
+    wt = workloads.fp32_rounded(workloads.perturbed(w, wl.extra["target_seed"]))
+    n, T = wl.nx, wl.T
+    shp = (n, n, n)
+    u0 = _pinned(shp, torch.float32)
+    workloads.uniform_into(u0.numpy(), wl.seed)
+    base = dict(ndim=3, nx=n, ny=n, nz=n, shape="star", radius=1, T=T, tb_depth=wl.tb_depth,
+                budget=wl.budget)
+    y = _pinned(shp, torch.float32)
+    pt = Plan(weights=list(wt), **base).bind()
+    pt.run_steps(u0, y, T)
+    pt.close()
+    uT = _pinned(shp, torch.float32)
+    pf = Plan(weights=list(w), **base).bind()
+    pf.run_steps(u0, uT, T)
+    pf.close()
+    pa = Plan(weights=list(w), adjoint=True, **base).bind()
+    _log(f"c5 plan {pa.info()}")
+    t0 = time.time()
+    loss, gu, gw, st = pa.adjoint(u0, y, wl.extra["ckpt_every"])
+    pa.close()
+    _log(f"c5 adjoint {time.time() - t0:.1f} s")
+    d = uT.numpy().astype(np.float64) - y.numpy()
+    ref_loss = 0.5 * float(np.sum(d * d))
+    inner = float(np.sum(d * uT.numpy()))
+    e_loss = abs(loss - ref_loss) / ref_loss
+    e_u0 = abs(float(np.sum(gu.numpy().astype(np.float64) * u0.numpy())) - inner) / abs(inner)
+    e_w = abs(float(np.dot(w, gw)) - T * inner) / abs(T * inner)
+    _log(f"c5 loss {e_loss:.2e}; <grad_u0,u0> identity {e_u0:.2e}; sum w dL/dw identity {e_w:.2e}")
+    assert e_loss <= 1e-10 and e_u0 <= 1e-4 and e_w <= 1e-4
+    # sampled box: lambda_0 = (A^T)^T (u_T - y) on B needs u_T - y on B + T r,
+    # i.e. u_T from u0 on B + 2 T r; y is the shared input array
+    lo, hi = np.array([500, 11, 700]), np.array([502, 13, 702])
+    R = T
+    lo1, hi1 = lo - R, hi + R
+    uTb = oracle.sweep_box_from_field(u0.numpy(), offs, w, T, lo1, hi1)
+    yb = oracle.extract_window(y.numpy(), lo1, hi1, (0, 0, 0))
+    lamT = uTb - yb
+    neg = [(-a, -b, -c) for a, b, c in offs]
+    lam0 = oracle.sweep_box_window(lamT, (n, n, n), neg, w, T, lo, hi)
+    g = gu.numpy()[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].astype(np.float64)
+    e_box = rel_l2(g, lam0)
+    _log(f"c5 grad_u0 sampled box rel L2 vs FP64 oracle {e_box:.2e}")
+    assert e_box <= 1e-4
