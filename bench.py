@@ -38,6 +38,12 @@ def parse():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-planes", type=int, default=0)
+    ap.add_argument("--compare-storage", default=None,
+                    help="also run this storage type on the same input and report the "
+                         "relative L2 deviation of the main run from it")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run plain device copies of 1 GiB (known bytes) so that "
+                         "hardware byte counters can be scaled")
     return ap.parse_args()
 
 
@@ -53,25 +59,26 @@ def weights_for(wl, offs):
     raise ValueError(wl.weights)
 
 
-def fill_input(wl, h):
+def draw_field(wl, dtype):
+    """The workload's initial field as a pinned host tensor of `dtype`
+    (float32 or float64), drawn block by block from the recipe's seed."""
+    import torch
     import workloads
-    a = h.numpy() if h.dtype.is_floating_point and h.element_size() >= 4 else None
-    if wl.init == "uniform" and a is not None:
-        workloads.uniform_into(a, wl.seed)
-    elif wl.init == "fourier" and a is not None:
-        workloads.fourier_modes_into(a, wl.seed)
-    elif wl.init == "bump" and a is not None:
-        workloads.gaussian_bump_into(a, wl.seed)
-    else:   # reduced storage: draw in FP32 block by block, round on copy
-        import torch
-        tmp = np.empty((min(16, h.shape[0]),) + tuple(h.shape[1:]), np.float32)
-        for z0 in range(0, h.shape[0], tmp.shape[0]):
-            z1 = min(h.shape[0], z0 + tmp.shape[0])
-            blk = np.empty((z1 - z0,) + tuple(h.shape[1:]), np.float32)
-            if wl.init == "bump":
-                full = None
-            workloads.uniform_into(blk, wl.seed + z0)
-            h[z0:z1].copy_(torch.from_numpy(blk))
+    gen = {"uniform": workloads.uniform_into, "fourier": workloads.fourier_modes_into,
+           "bump": workloads.gaussian_bump_into}[wl.init]
+    shape = (wl.ny, wl.nx) if wl.ndim == 2 else (wl.nz, wl.ny, wl.nx)
+    h = torch.empty(shape, dtype=dtype, pin_memory=True)
+    gen(h.numpy(), wl.seed)
+    return h
+
+
+def rounded_copy(src, dtype):
+    """Pinned copy of src rounded (nearest even) to dtype, plane block by block."""
+    import torch
+    h = torch.empty(src.shape, dtype=dtype, pin_memory=True)
+    for z0 in range(0, src.shape[0], 64):
+        h[z0:z0 + 64].copy_(src[z0:z0 + 64])
+    return h
 
 
 def cpu_baseline(wl, offs, w, planes):
@@ -105,6 +112,13 @@ def main():
     import workloads
     from paper_2309_08864_amd import Plan, stencil_offsets
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = workloads.CONFIGS[args.workload]
     storage = args.storage or wl.dtypes[0]
     offs = stencil_offsets(wl.ndim, wl.shape, wl.radius)
@@ -122,9 +136,12 @@ def main():
     tdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16,
            "f16": torch.float16}[storage]
     shape = (wl.ny, wl.nx) if wl.ndim == 2 else (wl.nz, wl.ny, wl.nx)
-    h = torch.empty(shape, dtype=tdt, pin_memory=True)
     t0 = time.perf_counter()
-    fill_input(wl, h)
+    if tdt in (torch.float32, torch.float64):
+        master = draw_field(wl, tdt)
+    else:   # reduced storage: the FP32 field rounded once to the storage type
+        master = draw_field(wl, torch.float32)
+    h = rounded_copy(master, tdt) if args.compare_storage or master.dtype != tdt else master
     print(f"# input ready in {time.perf_counter() - t0:.1f} s; plan {info}", file=sys.stderr,
           flush=True)
 
@@ -190,7 +207,42 @@ def main():
         "cpu_baseline": None,
     }
     plan.close()
-    del h
+    if args.compare_storage:
+        # same input in the other storage type (FP32 as the accuracy reference)
+        cdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16,
+               "f16": torch.float16}[args.compare_storage]
+        wr = weights_for(wl, offs)
+        if args.compare_storage != "f64":
+            wr = workloads.fp32_rounded(wr)
+        ref_plan = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape,
+                        radius=wl.radius, weights=list(wr), T=wl.T, tb_depth=K, n_chunks=d,
+                        n_slots=args.slots, budget=wl.budget, storage=args.compare_storage,
+                        bc=wl.periodic).bind()
+        hr = master if master.dtype == cdt else rounded_copy(master, cdt)
+        hm = rounded_copy(master, tdt)
+        t1 = time.perf_counter()
+        ref_plan.run(hr)
+        t_ref = time.perf_counter() - t1
+        plan2 = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
+                     weights=list(w), T=wl.T, tb_depth=K, n_chunks=d, k_on=args.k_on,
+                     n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic).bind()
+        plan2.run(hm)
+        plan2.close()
+        ref_plan.close()
+        num = den = 0.0
+        for z0 in range(0, shape[0], 32):
+            a_ = hm[z0:z0 + 32].double()
+            b_ = hr[z0:z0 + 32].double()
+            num += float(((a_ - b_) ** 2).sum())
+            den += float((b_ ** 2).sum())
+        res["precision"] = {
+            "reference_storage": args.compare_storage,
+            "rel_l2_vs_reference": (num / den) ** 0.5 if den else None,
+            "reference_GCells": round(wl.cells * wl.T / t_ref / 1e9, 3),
+            "speedup_vs_reference": round(value / (wl.cells * wl.T / t_ref / 1e9), 3),
+        }
+        del hr, hm
+    del h, master
     if not args.no_cpu_baseline:
         planes = args.cpu_sample_planes or 64
         res["cpu_baseline"] = cpu_baseline(wl, offs, w, planes)

@@ -88,6 +88,8 @@ typedef struct {
   size_t slot_bytes;          /* one slot: two ping-pong buffers (five with the adjoint) */
   size_t rs_bytes;            /* region-sharing buffer */
   size_t scratch_bytes;       /* reduction scratch (adjoint) */
+  int lean;                   /* 1: one buffer per slot, kernels in shifted sub-blocks */
+  int lean_block;             /* output planes per sub-block launch when lean */
   double redundant_fraction;  /* recomputed / useful cell updates */
   int64_t n_ops;              /* entries in the operation schedule */
 } so2dr_plan_info;
@@ -98,7 +100,9 @@ typedef enum {
   SO2DR_OP_H2D = 0,      /* host planes [z0,z1) -> slot buffer buf_out */
   SO2DR_OP_RS_READ = 1,  /* region-sharing buffer -> slot buffer buf_out planes [z0,z1) */
   SO2DR_OP_RS_WRITE = 2, /* slot buffer buf_in planes [z0,z1) -> region-sharing buffer */
-  SO2DR_OP_KERNEL = 3,   /* levels steps: buf_in (valid [in_z0,in_z1)) -> buf_out [z0,z1) */
+  SO2DR_OP_KERNEL = 3,   /* levels steps: buf_in (valid [in_z0,in_z1)) -> buf_out [z0,z1);
+                            in a lean plan buf_in == buf_out and the output lands below
+                            every input plane a later operation still reads */
   SO2DR_OP_D2H = 4       /* slot buffer buf_in planes [z0,z1) -> host planes [z0,z1) */
 } so2dr_op_kind;
 
@@ -110,7 +114,8 @@ typedef struct {
   int level_in;           /* KERNEL: time level (within the round) of the input */
   int levels;             /* KERNEL: steps fused in this launch */
   int buf_in, buf_out;    /* slot buffer index 0/1 (-1 when not used) */
-  int64_t buf_z0;         /* global plane held at index 0 of this chunk's slot buffers */
+  int64_t buf_z0;         /* global plane held at index 0 of the buffer read (or copied) */
+  int64_t out_z0;         /* KERNEL: global plane held at index 0 of the buffer written */
 } so2dr_op;
 
 /* Per-run measurements.  Times come from HIP events when timing is enabled

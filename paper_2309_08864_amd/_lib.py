@@ -39,7 +39,8 @@ class PlanInfo(ctypes.Structure):
                 ("max_chunk_planes", ctypes.c_int), ("slot_planes", ctypes.c_int),
                 ("max_k_on", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
                 ("slot_bytes", ctypes.c_size_t), ("rs_bytes", ctypes.c_size_t),
-                ("scratch_bytes", ctypes.c_size_t), ("redundant_fraction", ctypes.c_double),
+                ("scratch_bytes", ctypes.c_size_t), ("lean", ctypes.c_int),
+                ("lean_block", ctypes.c_int), ("redundant_fraction", ctypes.c_double),
                 ("n_ops", ctypes.c_int64)]
 
 
@@ -48,7 +49,7 @@ class Op(ctypes.Structure):
                 ("slot", ctypes.c_int), ("z0", ctypes.c_int64), ("z1", ctypes.c_int64),
                 ("in_z0", ctypes.c_int64), ("in_z1", ctypes.c_int64), ("level_in", ctypes.c_int),
                 ("levels", ctypes.c_int), ("buf_in", ctypes.c_int), ("buf_out", ctypes.c_int),
-                ("buf_z0", ctypes.c_int64)]
+                ("buf_z0", ctypes.c_int64), ("out_z0", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):

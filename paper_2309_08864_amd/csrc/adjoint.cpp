@@ -197,6 +197,7 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
           lp.in = buf(src);
           lp.out = buf(dst);
           lp.buf_z0 = bz;
+          lp.out_z0 = bz;
           lp.in_lo = area_lo(P, i, kp, done);
           lp.in_hi = area_hi(P, i, kp, done);
           lp.out_lo = area_lo(P, i, kp, done + kl);
@@ -225,6 +226,7 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
       lp.in = buf(lcur);
       lp.out = buf(lnext);
       lp.buf_z0 = bz;
+      lp.out_z0 = bz;
       lp.in_lo = area_lo(P, i, kp, st);
       lp.in_hi = area_hi(P, i, kp, st);
       lp.out_lo = area_lo(P, i, kp, st + 1);

@@ -90,6 +90,8 @@ int so2dr_plan_get_info(const so2dr_plan *plan, so2dr_plan_info *info) {
   info->slot_bytes = (size_t)P.bufs_per_slot * P.buf_bytes;
   info->rs_bytes = P.rs_bytes;
   info->scratch_bytes = P.scratch_bytes;
+  info->lean = P.lean ? 1 : 0;
+  info->lean_block = P.lean_block;
   int64_t computed = 0;
   auto ops = so2dr::build_ops(P, P.T, &computed);
   info->n_ops = (int64_t)ops.size();

@@ -25,7 +25,7 @@ struct LaunchParams {
   int kl;                  // fused levels
   const void *in;
   void *out;
-  int64_t buf_z0, plane;
+  int64_t buf_z0, out_z0, plane;   // global planes at index 0 of in and out
   int nx, ny, per_x, per_y;
   int64_t n_axis, in_lo, in_hi, out_lo, out_hi;
   const double *weights;   // npts, lexicographic

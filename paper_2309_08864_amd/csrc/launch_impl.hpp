@@ -58,6 +58,7 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   a.in = p.in;
   a.out = p.out;
   a.buf_z0 = p.buf_z0;
+  a.out_z0 = p.out_z0;
   a.plane = p.plane;
   a.nx = p.nx;
   a.ny = p.ny;
@@ -102,12 +103,12 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   return 0;
 }
 
-template <typename T, int R, int KL>
-int launch_star_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
+template <typename T, bool BOX, int R, int KL>
+int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
   constexpr int NW = SO2DR_STAR_NW, M = SO2DR_STAR_M, VX = SO2DR_STAR_VX, HB = SO2DR_STAR_HB;
   using G = StarTile<R, KL, NW, M, VX>;
-  using S = Stencil<3, false, R>;
+  using S = Stencil<3, BOX, R>;
   if (p.npts != S::npts()) {
     if (msg) *msg = "weight count does not match the stencil";
     return -1;
@@ -116,6 +117,7 @@ int launch_star_one(const LaunchParams &p, hipStream_t stream, std::string *msg)
   a.in = p.in;
   a.out = p.out;
   a.buf_z0 = p.buf_z0;
+  a.out_z0 = p.out_z0;
   a.plane = p.plane;
   a.nx = p.nx;
   a.ny = p.ny;
@@ -138,7 +140,8 @@ int launch_star_one(const LaunchParams &p, hipStream_t stream, std::string *msg)
     return -1;
   }
   const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
-  hipLaunchKernelGGL((star3d_kernel<T, R, KL, NW, M, VX, HB>), dim3((unsigned)grid), dim3(NW * 64), 0, stream, a);
+  hipLaunchKernelGGL((col3d_kernel<T, BOX, R, KL, NW, M, VX, HB>), dim3((unsigned)grid), dim3(NW * 64), 0,
+                     stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     if (msg) *msg = std::string("kernel launch: ") + hipGetErrorString(e);
@@ -147,15 +150,15 @@ int launch_star_one(const LaunchParams &p, hipStream_t stream, std::string *msg)
   return 0;
 }
 
-// 3D star stencils go to the register-column kernel, everything else to the
-// LDS-plane kernel; both compute the same bits.
+// 3D stencils go to the register-column kernel when its tile and LDS fit,
+// 2D ones to the LDS-plane kernel; both compute the same bits.
 template <typename T, int NDIM, bool BOX, int R, int KL>
 int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
   constexpr size_t star_lds =
       sizeof(typename Store<T>::A) * KL * SO2DR_STAR_HB * SO2DR_STAR_NW * 2 * R * 64 * SO2DR_STAR_VX;
-  if constexpr (NDIM == 3 && !BOX && SO2DR_STAR_KERNEL && (KL * R * 2 < SO2DR_STAR_NW * SO2DR_STAR_M) &&
+  if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && (KL * R * 2 < SO2DR_STAR_NW * SO2DR_STAR_M) &&
                 star_lds <= 65536)
-    return launch_star_one<T, R, KL>(p, s, msg);
+    return launch_col_one<T, BOX, R, KL>(p, s, msg);
   else
     return launch_one<T, NDIM, BOX, R, KL>(p, s, msg);
 }

@@ -88,7 +88,8 @@ std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_comput
     const int64_t h = 2 * (int64_t)P.r * kp;
     for (int i = 0; i < P.d; ++i) {
       const int slot = (int)(((int64_t)t * P.d + i) % P.n_slots);
-      const int64_t buf_z0 = area_lo(P, i, kp, 0);
+      // the round-start data sits lean_extra planes above index 0 (lean plans)
+      const int64_t buf_z0 = area_lo(P, i, kp, 0) - P.lean_extra;
       so2dr_op base;
       std::memset(&base, 0, sizeof(base));
       base.round = t;
@@ -97,6 +98,7 @@ std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_comput
       base.buf_in = -1;
       base.buf_out = -1;
       base.buf_z0 = buf_z0;
+      base.out_z0 = buf_z0;
       // host -> slot buffer 0: the chunk's own planes
       so2dr_op op = base;
       op.kind = SO2DR_OP_H2D;
@@ -123,6 +125,7 @@ std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_comput
       }
       // fused-step launches over the shrinking area
       int s = 0, j = 0;
+      int64_t cur_z0 = buf_z0;  // global plane at index 0 of the data being read
       while (s < kp) {
         const int kl = std::min(P.k_on, kp - s);
         op = base;
@@ -131,11 +134,31 @@ std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_comput
         op.levels = kl;
         op.in_z0 = area_lo(P, i, kp, s);
         op.in_z1 = area_hi(P, i, kp, s);
-        op.z0 = area_lo(P, i, kp, s + kl);
-        op.z1 = area_hi(P, i, kp, s + kl);
-        op.buf_in = j & 1;
-        op.buf_out = (j + 1) & 1;
-        ops.push_back(op);
+        const int64_t o0 = area_lo(P, i, kp, s + kl), o1 = area_hi(P, i, kp, s + kl);
+        if (!P.lean) {
+          op.z0 = o0;
+          op.z1 = o1;
+          op.buf_in = j & 1;
+          op.buf_out = (j + 1) & 1;
+          op.buf_z0 = cur_z0;
+          op.out_z0 = cur_z0;
+          ops.push_back(op);
+        } else {
+          // one buffer: output sub-blocks of B planes in ascending order, each
+          // written B + kl r planes below where it reads, i.e. over planes no
+          // later sub-block reads (it needs planes >= its own start - kl r)
+          const int64_t shift = P.lean_block + (int64_t)kl * P.r;
+          op.buf_in = 0;
+          op.buf_out = 0;
+          op.buf_z0 = cur_z0;
+          op.out_z0 = cur_z0 + shift;
+          for (int64_t b = o0; b < o1; b += P.lean_block) {
+            op.z0 = b;
+            op.z1 = std::min(o1, b + (int64_t)P.lean_block);
+            ops.push_back(op);
+          }
+          cur_z0 += shift;
+        }
         for (int q = s + 1; q <= s + kl; ++q) computed += area_hi(P, i, kp, q) - area_lo(P, i, kp, q);
         s += kl;
         ++j;
@@ -145,7 +168,8 @@ std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_comput
       op.kind = SO2DR_OP_D2H;
       op.z0 = area_lo(P, i, kp, kp);
       op.z1 = area_hi(P, i, kp, kp);
-      op.buf_in = j & 1;
+      op.buf_in = P.lean ? 0 : (j & 1);
+      op.buf_z0 = cur_z0;
       ops.push_back(op);
     }
   }
@@ -153,14 +177,27 @@ std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_comput
   return ops;
 }
 
-// Byte total of a candidate (d, slots) plan; fills the sizes into P.
-static size_t plan_bytes(Plan &P, int d, int slots) {
+// Byte total of a candidate (d, slots) plan; fills the sizes into P.  A lean
+// plan keeps one buffer per slot with lean_extra spare planes below the data:
+// every launch moves the data B + k r planes down while the valid area's
+// bottom rises by k r (or not at all for the first chunk).
+static size_t plan_bytes(Plan &P, int d, int slots, bool lean = false) {
   P.d = d;
   P.bnd.assign(d + 1, 0);
   for (int i = 0; i <= d; ++i) P.bnd[i] = (P.N * i) / d;
   const int64_t halo = d > 1 ? 2 * (int64_t)P.r * P.K : 0;
   int64_t sp = 0;
   for (int i = 0; i < d; ++i) sp = std::max<int64_t>(sp, P.bnd[i + 1] - P.bnd[i] + (i > 0 ? halo : 0));
+  P.lean = lean;
+  if (lean) {
+    const int n_launch = (P.K + P.k_on - 1) / P.k_on;
+    P.lean_block = (int)std::max<int64_t>(1, std::min<int64_t>(16, sp / 8));
+    P.lean_extra = (int64_t)n_launch * P.lean_block + (int64_t)P.K * P.r;
+    sp += P.lean_extra;
+  } else {
+    P.lean_block = 0;
+    P.lean_extra = 0;
+  }
   P.slot_planes = sp;
   P.buf_bytes = align256((size_t)sp * P.plane_bytes());
   P.rs_bytes = align256((size_t)halo * P.plane_bytes());
@@ -168,7 +205,7 @@ static size_t plan_bytes(Plan &P, int d, int slots) {
   // adjoint: per slot the round-start state, a recompute pair and the
   // adjoint pair; a second region-sharing buffer for the adjoint field; FP64
   // partial sums for the loss and weight-gradient reductions
-  P.bufs_per_slot = P.adjoint ? 5 : 2;
+  P.bufs_per_slot = P.adjoint ? 5 : (lean ? 1 : 2);
   P.scratch_bytes = P.adjoint ? align256(sizeof(double) * (kRedWgs * kMaxRedPts + 256)) : 0;
   return (size_t)slots * P.bufs_per_slot * P.buf_bytes + (size_t)P.n_rs() * P.rs_bytes +
          P.scratch_bytes;
@@ -261,11 +298,20 @@ int make_plan(const so2dr_desc &D, Plan *P) {
       if (D.n_slots > 0) { slots = 0; break; }
       --slots;
     }
+    bool lean = false;
+    if (slots < 1 && !P->adjoint) {  // one buffer per slot instead of two
+      slots = want;
+      while (slots >= 1 && plan_bytes(*P, D.n_chunks, slots, true) > P->budget) {
+        if (D.n_slots > 0) { slots = 0; break; }
+        --slots;
+      }
+      lean = slots >= 1;
+    }
     if (slots < 1) {
       set_error("plan does not fit the device budget (chunks " + std::to_string(D.n_chunks) + ")");
       return SO2DR_E_BUDGET;
     }
-    plan_bytes(*P, D.n_chunks, slots);
+    plan_bytes(*P, D.n_chunks, slots, lean);
   } else {
     // fewest chunks that fit with min(3, d) slots; else the fewest that fit at all
     int chosen = 0, chosen_slots = 0;
@@ -277,8 +323,14 @@ int make_plan(const so2dr_desc &D, Plan *P) {
           if (plan_bytes(*P, d, slots) <= P->budget) { chosen = d; chosen_slots = slots; break; }
       }
     }
+    bool lean = false;
+    for (int d = 1; !chosen && !P->adjoint && d <= P->N; ++d) {  // lean layout as a last resort
+      if (!chunks_ok(*P, d)) break;
+      for (int slots = D.n_slots > 0 ? D.n_slots : std::min(3, d); slots >= 1; --slots)
+        if (plan_bytes(*P, d, slots, true) <= P->budget) { chosen = d; chosen_slots = slots; lean = true; break; }
+    }
     if (!chosen) { set_error("no chunk count fits the device budget"); return SO2DR_E_BUDGET; }
-    plan_bytes(*P, chosen, chosen_slots);
+    plan_bytes(*P, chosen, chosen_slots, lean);
   }
   P->workspace = (size_t)P->n_slots * P->bufs_per_slot * P->buf_bytes + (size_t)P->n_rs() * P->rs_bytes +
                  P->scratch_bytes;

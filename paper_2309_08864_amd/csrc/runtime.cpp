@@ -226,6 +226,7 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
         lp.in = P.slot_buf(op.slot, op.buf_in);
         lp.out = P.slot_buf(op.slot, op.buf_out);
         lp.buf_z0 = op.buf_z0;
+        lp.out_z0 = op.out_z0;
         lp.plane = P.plane;
         lp.nx = (int)P.NX;
         lp.ny = (int)P.NY;

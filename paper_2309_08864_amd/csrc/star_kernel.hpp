@@ -1,4 +1,5 @@
-// star_kernel.hpp -- fused-step kernel specialised for 3D star stencils.
+// star_kernel.hpp -- register-column fused-step kernel for 3D star and box
+// stencils.
 //
 // Same contract and the same per-cell arithmetic as tb_kernel (each output's
 // FMA chain in lexicographic (dz, dy, dx) order, partial sums advanced as
@@ -107,10 +108,10 @@ struct StarTile {
   static_assert(M >= R && R <= VX && OX > 0 && OY > 0, "tile too small for this depth");
 };
 
-template <typename T, int R, int KL, int NW, int M, int VX_, int HB>
-__global__ __launch_bounds__(NW * 64) void star3d_kernel(const TbArgs<typename Store<T>::A> a) {
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX_, int HB>
+__global__ __launch_bounds__(NW * 64) void col3d_kernel(const TbArgs<typename Store<T>::A> a) {
   using A = typename Store<T>::A;
-  using S = Stencil<3, false, R>;
+  using S = Stencil<3, BOX, R>;
   using G = StarTile<R, KL, NW, M, VX_>;
   constexpr int W = 2 * R + 1, VX = G::VX;
   // wave boundary rows (top R then bottom R) of every level; HB = 2 buffers
@@ -258,33 +259,36 @@ __global__ __launch_bounds__(NW * 64) void star3d_kernel(const TbArgs<typename S
       for (int m = 0; m < M; ++m)
 #pragma unroll
         for (int j = 0; j < VX; ++j) col[R + m][j] = l == 1 ? cur[m][j] : done[l - 1][m][j];
+      // every row of the consumed plane, extended by R cells from each
+      // neighbouring lane (unused extensions are dead code for stars)
+      A row[M + 2 * R][VX + 2 * R];
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        // this row with R cells from each neighbouring lane
-        A row[VX + 2 * R];
-        A res_row[VX];
+      for (int i = 0; i < M + 2 * R; ++i) {
 #pragma unroll
-        for (int j = 0; j < VX; ++j) row[R + j] = col[R + m][j];
+        for (int j = 0; j < VX; ++j) row[i][R + j] = col[i][j];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          row[R - 1 - r] = dpp_f<kDppWaveShr1>(col[R + m][VX - 1 - r]);
-          row[R + VX + r] = dpp_f<kDppWaveShl1>(col[R + m][r]);
+          row[i][R - 1 - r] = dpp_f<kDppWaveShr1>(col[i][VX - 1 - r]);
+          row[i][R + VX + r] = dpp_f<kDppWaveShl1>(col[i][r]);
         }
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        A res_row[VX];
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
-          const A own = row[R + j];
-          A s = acc[l - 1][m][j][R];
-#pragma unroll
-          for (int dy = -R; dy <= -1; ++dy) s = fma_(a.w.w[S::table.idx[R][dy + R][R]], col[R + m + dy][j], s);
-#pragma unroll
-          for (int dx = -R; dx <= R; ++dx) s = fma_(a.w.w[S::table.idx[R][R][dx + R]], row[R + j + dx], s);
-#pragma unroll
-          for (int dy = 1; dy <= R; ++dy) s = fma_(a.w.w[S::table.idx[R][dy + R][R]], col[R + m + dy][j], s);
-          acc[l - 1][m][j][R] = s;
+          // the plane's terms for each output it feeds, lexicographic (dy, dx)
 #pragma unroll
           for (int dz = -R; dz <= R; ++dz) {
-            if (dz == 0) continue;
-            acc[l - 1][m][j][R + dz] = fma_(a.w.w[S::table.idx[dz + R][R][R]], own, acc[l - 1][m][j][R + dz]);
+            A s = acc[l - 1][m][j][R + dz];
+#pragma unroll
+            for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+              for (int dx = -R; dx <= R; ++dx) {
+                const int wi = S::table.idx[dz + R][dy + R][dx + R];
+                if (wi >= 0) s = fma_(a.w.w[wi], row[R + m + dy][R + j + dx], s);
+              }
+            acc[l - 1][m][j][R + dz] = s;
           }
           A res = Store<T>::round(acc[l - 1][m][j][2 * R]);
           if (zghost || ghy[m] || ghx[j]) res = A(0);
@@ -295,7 +299,7 @@ __global__ __launch_bounds__(NW * 64) void star3d_kernel(const TbArgs<typename S
           else res_row[j] = res;
         }
         if (l == KL && outy[m] && q >= zo0 && q < zo1) {
-          T *dst = out + (q - a.buf_z0) * a.plane + rowoff[m];
+          T *dst = out + (q - a.out_z0) * a.plane + rowoff[m];
           if (out_vec) {
             VecIO<T, VX>::store(dst + gx0, res_row);
           } else {

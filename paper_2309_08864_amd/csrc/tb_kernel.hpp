@@ -59,7 +59,8 @@ template <typename A>
 struct TbArgs {
   const void *in;
   void *out;
-  int64_t buf_z0;          // global plane stored at index 0 of in/out
+  int64_t buf_z0;          // global plane stored at index 0 of in
+  int64_t out_z0;          // global plane stored at index 0 of out
   int64_t plane;           // elements per plane (nx * ny)
   int nx, ny;              // in-plane extents (ny == 1 for a 2D grid)
   int per_x, per_y;        // periodic flags of the in-plane axes
@@ -313,9 +314,9 @@ __global__ __launch_bounds__(256) void tb_kernel(const TbArgs<typename Store<T>:
           done[l][c] = res;
         } else if (outc[c] && q >= zo0 && q < zo1) {
 #if SO2DR_NT_STORE
-          __builtin_nontemporal_store(res, out + (q - a.buf_z0) * a.plane + goff[c]);
+          __builtin_nontemporal_store(res, out + (q - a.out_z0) * a.plane + goff[c]);
 #else
-          Store<T>::store(out + (q - a.buf_z0) * a.plane + goff[c], res);
+          Store<T>::store(out + (q - a.out_z0) * a.plane + goff[c], res);
 #endif
         }
       }

@@ -199,3 +199,27 @@ def test_edge_cases():
     with pytest.raises(So2drError, match="E_NOT_PINNED"):
         p.run(u0.clone())
     p.close()
+
+
+@pytest.mark.parametrize("ndim,shape,r,storage", [(3, "star", 1, "f32"), (3, "box", 1, "f32"),
+                                                  (3, "star", 2, "bf16"), (2, "box", 2, "f32"),
+                                                  (3, "star", 1, "f64")])
+def test_lean_layout_bitwise(ndim, shape, r, storage):
+    """One buffer per slot (kernels split into sub-blocks that write below
+    what later sub-blocks read) gives the in-core bits."""
+    from paper_2309_08864_amd import Plan
+    rng = np.random.default_rng(81 + r)
+    offs = _offsets(ndim, shape, r)
+    w = _weights(offs, rng)
+    nx, ny, nz = _dims(ndim)
+    u0 = rng.random(np_shape(ndim, nx, ny, nz))
+    us = to_storage(u0, storage)
+    T, K = 8, 4 if r == 1 else 3
+    d = 3 if r == 1 else 2
+    kw = _kwargs(ndim, shape, r, w, T, K, d, 2, storage=storage, slots=1)
+    full = Plan(**kw).info()["workspace_bytes"]
+    lean_kw = dict(kw, budget=full - 1)
+    assert Plan(**lean_kw).info()["lean"] == 1
+    got, _, info = gpu_run(lean_kw, us)
+    incore, _, _ = gpu_run(_kwargs(ndim, shape, r, w, T, T, 1, 1, storage=storage), us)
+    assert torch.equal(got, incore)

@@ -117,6 +117,26 @@ def test_paper_configuration_fits_and_counts():
     assert sum(1 for o in ops if o["kind"] == "KERNEL") == 4 * 4 * 40
 
 
+def test_lean_layout_for_the_2d_fp64_workload():
+    """Four 256-row FP64 chunks need 4.19 MiB with two buffers per slot; the
+    one-buffer layout fits the 4 MiB budget, and its schedule replays on the
+    CPU against the oracle."""
+    offs, w = _w(2, "star", 1)
+    w = [0.2] * 5
+    p = Plan(ndim=2, nx=1024, ny=1024, nz=1, shape="star", radius=1, weights=w, T=16, tb_depth=4,
+             n_chunks=4, budget=4 << 20, storage="f64")
+    info = p.info()
+    assert info["lean"] == 1 and info["workspace_bytes"] <= 4 << 20
+    ps = Plan(ndim=2, nx=16, ny=1024, nz=1, shape="star", radius=1, weights=w, T=16, tb_depth=4,
+              n_chunks=4, budget=info["workspace_bytes"] // 64, storage="f64")
+    assert ps.info()["lean"] == 1
+    rng = np.random.default_rng(1)
+    u0 = rng.random((1024, 1, 16))
+    host, lv = simulate(ps, offs, w, u0, 0, 0, 2)
+    ref = oracle.sweep(u0[:, 0, :], offs, w, 16)[:, None, :]
+    assert np.all(lv == 16) and np.allclose(host, ref, rtol=1e-12, atol=1e-12)
+
+
 def test_budget_accounting_and_auto_plan():
     offs, w = _w(3, "star", 1)
     kw = dict(ndim=3, nx=2048, ny=1024, nz=1024, shape="star", radius=1, weights=w, T=64, tb_depth=8)
@@ -187,7 +207,9 @@ def _np_step(win, offs, w, per_x, per_y):
 
 
 def simulate(p, offs, w, u0, per_x=0, per_y=0, ndim=3):
-    """Replay p.ops() on host arrays.  u0: (N, ny, nx)."""
+    """Replay p.ops() on host arrays.  u0: (N, ny, nx).  Every buffer index an
+    operation touches is checked against the slot size, and every plane a
+    kernel needs must hold the level it expects."""
     info = p.info()
     N = info["n_axis"]
     r = max(max(abs(c) for c in o) for o in offs)
@@ -202,6 +224,12 @@ def simulate(p, offs, w, u0, per_x=0, per_y=0, ndim=3):
     pool = np.zeros((2 * r * info["tb_depth"],) + shp)
     pool_lvl = np.full(pool.shape[0], -1)
     round_start = 0
+
+    def idx(z0, z1, base):
+        i0, i1 = z0 - base, z1 - base
+        assert 0 <= i0 <= i1 <= S, f"buffer index [{i0}, {i1}) outside [0, {S})"
+        return slice(i0, i1)
+
     for op in p.ops():
         sl = op["slot"]
         if sl not in bufs:
@@ -212,48 +240,53 @@ def simulate(p, offs, w, u0, per_x=0, per_y=0, ndim=3):
         if kind == "H2D":
             round_start = int(host_lvl[z0])
             assert np.all(host_lvl[z0:z1] == round_start), "host planes not at round-start level"
-            bufs[sl][op["buf_out"]][z0 - b0:z1 - b0] = host[z0:z1]
-            lvl[sl][op["buf_out"]][z0 - b0:z1 - b0] = round_start
+            bufs[sl][op["buf_out"]][idx(z0, z1, b0)] = host[z0:z1]
+            lvl[sl][op["buf_out"]][idx(z0, z1, b0)] = round_start
         elif kind == "RS_READ":
             n = z1 - z0
             assert np.all(pool_lvl[:n] == round_start), "stale region-sharing data"
-            bufs[sl][op["buf_out"]][z0 - b0:z1 - b0] = pool[:n]
-            lvl[sl][op["buf_out"]][z0 - b0:z1 - b0] = round_start
+            bufs[sl][op["buf_out"]][idx(z0, z1, b0)] = pool[:n]
+            lvl[sl][op["buf_out"]][idx(z0, z1, b0)] = round_start
         elif kind == "RS_WRITE":
             n = z1 - z0
             src = bufs[sl][op["buf_in"]]
-            assert np.all(lvl[sl][op["buf_in"]][z0 - b0:z1 - b0] == round_start)
-            pool[:n] = src[z0 - b0:z1 - b0]
+            assert np.all(lvl[sl][op["buf_in"]][idx(z0, z1, b0)] == round_start)
+            pool[:n] = src[idx(z0, z1, b0)]
             pool_lvl[:n] = round_start
         elif kind == "KERNEL":
             L = op["levels"]
             s0 = round_start + op["level_in"]
             src, slv = bufs[sl][op["buf_in"]], lvl[sl][op["buf_in"]]
-            # planes [lo, hi) of the current level in global indices (zeros outside [0, N))
-            cur_lo, cur_hi = op["in_z0"], op["in_z1"]
-            assert np.all(slv[cur_lo - b0:cur_hi - b0] == s0), "kernel input not valid"
-            cur = src[cur_lo - b0:cur_hi - b0].copy()
+            # planes this launch needs, inside the input's valid area
+            cur_lo, cur_hi = max(0, z0 - L * r), min(N, z1 + L * r)
+            assert op["in_z0"] <= cur_lo and cur_hi <= op["in_z1"]
+            assert np.all(slv[idx(cur_lo, cur_hi, b0)] == s0), "kernel input not valid (halo too thin or overwritten)"
+            cur = src[idx(cur_lo, cur_hi, b0)].copy()
             for j in range(1, L + 1):
-                need_lo = op["z0"] - (L - j) * r
-                need_hi = op["z1"] + (L - j) * r
-                new_lo, new_hi = max(need_lo, 0), min(need_hi, N)
-                # window of the previous level [new_lo - r, new_hi + r), zero outside the grid
+                new_lo = max(z0 - (L - j) * r, 0)
+                new_hi = min(z1 + (L - j) * r, N)
                 win = np.zeros((new_hi - new_lo + 2 * r,) + shp)
                 for q in range(new_lo - r, new_hi + r):
                     if 0 <= q < N:
-                        assert cur_lo <= q < cur_hi, f"plane {q} needed but not valid (halo too thin)"
+                        assert cur_lo <= q < cur_hi, f"plane {q} needed but not loaded"
                         win[q - (new_lo - r)] = cur[q - cur_lo]
                 cur = _np_step(win, offs, w, per_x, per_y)
                 cur_lo, cur_hi = new_lo, new_hi
-            assert (cur_lo, cur_hi) == (op["z0"], op["z1"])
+            assert (cur_lo, cur_hi) == (z0, z1)
             dst, dlv = bufs[sl][op["buf_out"]], lvl[sl][op["buf_out"]]
-            dst[cur_lo - b0:cur_hi - b0] = cur
-            dlv[cur_lo - b0:cur_hi - b0] = s0 + L
+            if op["buf_out"] == op["buf_in"]:
+                # one launch reads and writes the same buffer concurrently: the
+                # index ranges must not meet
+                rd = idx(max(0, z0 - L * r), min(N, z1 + L * r), b0)
+                wr = idx(z0, z1, op["out_z0"])
+                assert wr.stop <= rd.start or rd.stop <= wr.start, "launch overwrites its own input"
+            dst[idx(z0, z1, op["out_z0"])] = cur
+            dlv[idx(z0, z1, op["out_z0"])] = s0 + L
         elif kind == "D2H":
             src, slv = bufs[sl][op["buf_in"]], lvl[sl][op["buf_in"]]
-            lv = slv[z0 - b0:z1 - b0]
+            lv = slv[idx(z0, z1, b0)]
             assert np.all(lv == lv[0]) and lv[0] > round_start
-            host[z0:z1] = src[z0 - b0:z1 - b0]
+            host[z0:z1] = src[idx(z0, z1, b0)]
             host_lvl[z0:z1] = lv[0]
     assert np.all(host_lvl == host_lvl[0])
     return host, host_lvl
@@ -264,10 +297,18 @@ def simulate(p, offs, w, u0, per_x=0, per_y=0, ndim=3):
     (3, "box", 1, 8, 4, 5, 3, (1, 1)), (2, "box", 2, 7, 3, 3, 2, (1, 0)),
     (2, "star", 1, 16, 4, 4, 4, (0, 0)), (3, "star", 1, 5, 5, 1, 2, (0, 0)),
     (3, "box", 1, 11, 3, 6, 3, (1, 0)), (2, "box", 4, 6, 2, 3, 1, (0, 0))])
-def test_schedule_simulator_matches_oracle(ndim, shape, r, T, K, d, k_on, per):
+@pytest.mark.parametrize("lean", [False, True])
+def test_schedule_simulator_matches_oracle(ndim, shape, r, T, K, d, k_on, per, lean):
     nx, ny, N = 7, 5, 48
+    budget = 1 << 30
+    if lean:   # just under what two buffers per slot need with one slot
+        p0, _, _ = _plan(ndim=ndim, nx=nx, ny=ny, nz=N, shape=shape, r=r, T=T, K=K, d=d, k_on=k_on,
+                         slots=1, bc=(per[0], per[1] if ndim == 3 else 0, 0))
+        budget = p0.info()["workspace_bytes"] - 1
     p, offs, w = _plan(ndim=ndim, nx=nx, ny=ny, nz=N, shape=shape, r=r, T=T, K=K, d=d, k_on=k_on,
+                       slots=1 if lean else 0, budget=budget,
                        bc=(per[0], per[1] if ndim == 3 else 0, 0))
+    assert p.info()["lean"] == (1 if lean else 0)
     rng = np.random.default_rng(T * 7 + K)
     if ndim == 3:
         u0 = rng.random((N, ny, nx))

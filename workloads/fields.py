@@ -66,7 +66,7 @@ def fourier_modes(shape, seed, noise_std=0.01):
     return fourier_modes_into(out, seed, noise_std)
 
 
-def gaussian_bump_into(out, seed, noise=1e-3, block=8):
+def gaussian_bump_into(out, seed, noise=1e-3, block=32):
     """exp(-|x - c|^2 / (2 sigma^2)) with c the grid centre ((n-1)/2 per axis)
     and sigma = n/8 per axis, plus U[-noise, noise) from PCG64(seed), block by
     block along the slowest axis."""
