@@ -56,6 +56,13 @@ typedef enum { SO2DR_F32 = 0, SO2DR_F64 = 1, SO2DR_BF16 = 2, SO2DR_F16 = 3 } so2
 typedef enum { SO2DR_STAR = 0, SO2DR_BOX = 1 } so2dr_shape;
 typedef enum { SO2DR_DIRICHLET0 = 0, SO2DR_PERIODIC = 1 } so2dr_bc;
 
+/* Out-of-core method.  SO2DR (Sec. IV): round-start planes shared once per
+ * round, overlap recomputed, k_on-step kernels.  RESREU (the paper's
+ * comparison code, Sec. II-B / Fig. 2): intermediate results of every step
+ * shared through the region-sharing buffer, so every kernel runs one step
+ * and nothing is recomputed; kept for comparison. */
+typedef enum { SO2DR_METHOD_SO2DR = 0, SO2DR_METHOD_RESREU = 1 } so2dr_method;
+
 /* Problem and run-time configuration: the variables of the paper's Table I
  * (dim, sz, r, d, S_tot, S_TB, N_strm, C_dmem) plus the stencil itself. */
 typedef struct {
@@ -74,6 +81,7 @@ typedef struct {
   int n_slots;                /* in-flight chunks (= streams); 0 = automatic, at most 3 */
   size_t device_budget_bytes; /* hard cap on the device memory the plan may use */
   int adjoint;                /* 1: also reserve what so2dr_adjoint_run needs */
+  int method;                 /* so2dr_method: SO2DR_METHOD_SO2DR (default) or _RESREU */
 } so2dr_desc;
 
 /* What the planner chose (all sizes in bytes unless noted). */
@@ -90,6 +98,7 @@ typedef struct {
   size_t scratch_bytes;       /* reduction scratch (adjoint) */
   int lean;                   /* 1: one buffer per slot, kernels in shifted sub-blocks */
   int lean_block;             /* output planes per sub-block launch when lean */
+  int method;                 /* so2dr_method of the plan */
   double redundant_fraction;  /* recomputed / useful cell updates */
   int64_t n_ops;              /* entries in the operation schedule */
 } so2dr_plan_info;
@@ -116,6 +125,7 @@ typedef struct {
   int buf_in, buf_out;    /* slot buffer index 0/1 (-1 when not used) */
   int64_t buf_z0;         /* global plane held at index 0 of the buffer read (or copied) */
   int64_t out_z0;         /* KERNEL: global plane held at index 0 of the buffer written */
+  int64_t pool_off;       /* RS_READ/RS_WRITE: first plane used in the region-sharing buffer */
 } so2dr_op;
 
 /* Per-run measurements.  Times come from HIP events when timing is enabled

@@ -13,6 +13,7 @@ ERROR_NAMES = {E_INVALID: "E_INVALID", E_BUDGET: "E_BUDGET", E_UNSUPPORTED: "E_U
                E_NOT_PINNED: "E_NOT_PINNED", E_HIP: "E_HIP", E_UNBOUND: "E_UNBOUND"}
 DTYPES = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3}
 SHAPES = {"star": 0, "box": 1}
+METHODS = {"so2dr": 0, "resreu": 1}
 OP_KINDS = {0: "H2D", 1: "RS_READ", 2: "RS_WRITE", 3: "KERNEL", 4: "D2H"}
 
 # Symbols the header declares; the CPU test checks each is exported.
@@ -29,7 +30,7 @@ class Desc(ctypes.Structure):
                 ("bc", ctypes.c_int * 3), ("storage", ctypes.c_int), ("T", ctypes.c_int),
                 ("n_chunks", ctypes.c_int), ("tb_depth", ctypes.c_int), ("k_on", ctypes.c_int),
                 ("n_slots", ctypes.c_int), ("device_budget_bytes", ctypes.c_size_t),
-                ("adjoint", ctypes.c_int)]
+                ("adjoint", ctypes.c_int), ("method", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -40,7 +41,8 @@ class PlanInfo(ctypes.Structure):
                 ("max_k_on", ctypes.c_int), ("workspace_bytes", ctypes.c_size_t),
                 ("slot_bytes", ctypes.c_size_t), ("rs_bytes", ctypes.c_size_t),
                 ("scratch_bytes", ctypes.c_size_t), ("lean", ctypes.c_int),
-                ("lean_block", ctypes.c_int), ("redundant_fraction", ctypes.c_double),
+                ("lean_block", ctypes.c_int), ("method", ctypes.c_int),
+                ("redundant_fraction", ctypes.c_double),
                 ("n_ops", ctypes.c_int64)]
 
 
@@ -49,7 +51,8 @@ class Op(ctypes.Structure):
                 ("slot", ctypes.c_int), ("z0", ctypes.c_int64), ("z1", ctypes.c_int64),
                 ("in_z0", ctypes.c_int64), ("in_z1", ctypes.c_int64), ("level_in", ctypes.c_int),
                 ("levels", ctypes.c_int), ("buf_in", ctypes.c_int), ("buf_out", ctypes.c_int),
-                ("buf_z0", ctypes.c_int64), ("out_z0", ctypes.c_int64)]
+                ("buf_z0", ctypes.c_int64), ("out_z0", ctypes.c_int64),
+                ("pool_off", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):

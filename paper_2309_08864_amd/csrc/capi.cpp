@@ -92,6 +92,7 @@ int so2dr_plan_get_info(const so2dr_plan *plan, so2dr_plan_info *info) {
   info->scratch_bytes = P.scratch_bytes;
   info->lean = P.lean ? 1 : 0;
   info->lean_block = P.lean_block;
+  info->method = P.resreu ? SO2DR_METHOD_RESREU : SO2DR_METHOD_SO2DR;
   int64_t computed = 0;
   auto ops = so2dr::build_ops(P, P.T, &computed);
   info->n_ops = (int64_t)ops.size();

@@ -29,6 +29,7 @@ struct Plan {
   size_t rs_bytes = 0, scratch_bytes = 0, workspace = 0, budget = 0;
   bool adjoint = false;
   int bufs_per_slot = 2;           // 2 ping-pong buffers; 5 when the adjoint is planned
+  bool resreu = false;             // comparison method: per-step sharing, single-step kernels
   bool lean = false;               // 1 buffer per slot, kernels split into shifted sub-blocks
   int lean_block = 0;              // output planes per sub-block launch
   int64_t lean_extra = 0;          // spare planes below the round-start data

@@ -71,12 +71,77 @@ int round_depth(const Plan &P, int steps, int t) {
 
 int64_t area_lo(const Plan &P, int i, int kp, int s) {
   if (i == 0) return 0;
+  if (P.resreu) return P.bnd[i] - (int64_t)s * P.r;  // no redundant overlap
   return P.bnd[i] - 2 * (int64_t)P.r * kp + (int64_t)s * P.r;
 }
 
 int64_t area_hi(const Plan &P, int i, int kp, int s) {
   if (i == P.d - 1) return P.N;
   return P.bnd[i + 1] - (int64_t)s * P.r;
+}
+
+// The comparison method (paper Sec. II-B, Fig. 2): before step s of a round,
+// chunk i takes the 2r planes of level s-1 just below its level-(s-1) area,
+// [b_{i-1} - r(s+1), b_{i-1} - r(s-1)), from the sharing buffer (pool slot
+// s-1, written by chunk i-1 during its own step s), then leaves its own
+// top 2r planes of level s-1 there for chunk i+1, then runs one step.
+static void build_resreu_chunk(const Plan &P, int t, int i, int kp, int slot,
+                               std::vector<so2dr_op> &ops, int64_t *computed) {
+  const int64_t r = P.r;
+  so2dr_op base;
+  std::memset(&base, 0, sizeof(base));
+  base.round = t;
+  base.chunk = i;
+  base.slot = slot;
+  base.buf_in = -1;
+  base.buf_out = -1;
+  base.buf_z0 = i == 0 ? 0 : P.bnd[i] - r * (P.K + 1);
+  base.out_z0 = base.buf_z0;
+  so2dr_op op = base;
+  op.kind = SO2DR_OP_H2D;
+  op.z0 = P.bnd[i];
+  op.z1 = P.bnd[i + 1];
+  op.buf_out = 0;
+  ops.push_back(op);
+  for (int st = 1; st <= kp; ++st) {
+    const int in_buf = (st - 1) & 1;
+    if (i > 0) {
+      op = base;
+      op.kind = SO2DR_OP_RS_READ;
+      op.z0 = P.bnd[i] - r * (st + 1);
+      op.z1 = P.bnd[i] - r * (st - 1);
+      op.buf_out = in_buf;
+      op.pool_off = 2 * r * (st - 1);
+      ops.push_back(op);
+    }
+    if (i < P.d - 1) {
+      op = base;
+      op.kind = SO2DR_OP_RS_WRITE;
+      op.z0 = P.bnd[i + 1] - r * (st + 1);
+      op.z1 = P.bnd[i + 1] - r * (st - 1);
+      op.buf_in = in_buf;
+      op.pool_off = 2 * r * (st - 1);
+      ops.push_back(op);
+    }
+    op = base;
+    op.kind = SO2DR_OP_KERNEL;
+    op.level_in = st - 1;
+    op.levels = 1;
+    op.in_z0 = i == 0 ? 0 : P.bnd[i] - r * (st + 1);
+    op.in_z1 = area_hi(P, i, kp, st - 1);
+    op.z0 = area_lo(P, i, kp, st);
+    op.z1 = area_hi(P, i, kp, st);
+    op.buf_in = in_buf;
+    op.buf_out = st & 1;
+    ops.push_back(op);
+    *computed += op.z1 - op.z0;
+  }
+  op = base;
+  op.kind = SO2DR_OP_D2H;
+  op.z0 = area_lo(P, i, kp, kp);
+  op.z1 = area_hi(P, i, kp, kp);
+  op.buf_in = kp & 1;
+  ops.push_back(op);
 }
 
 std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_computed) {
@@ -88,6 +153,10 @@ std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_comput
     const int64_t h = 2 * (int64_t)P.r * kp;
     for (int i = 0; i < P.d; ++i) {
       const int slot = (int)(((int64_t)t * P.d + i) % P.n_slots);
+      if (P.resreu) {
+        build_resreu_chunk(P, t, i, kp, slot, ops, &computed);
+        continue;
+      }
       // the round-start data sits lean_extra planes above index 0 (lean plans)
       const int64_t buf_z0 = area_lo(P, i, kp, 0) - P.lean_extra;
       so2dr_op base;
@@ -186,8 +255,11 @@ static size_t plan_bytes(Plan &P, int d, int slots, bool lean = false) {
   P.bnd.assign(d + 1, 0);
   for (int i = 0; i <= d; ++i) P.bnd[i] = (P.N * i) / d;
   const int64_t halo = d > 1 ? 2 * (int64_t)P.r * P.K : 0;
+  // below its own planes a chunk holds the 2rK-plane shared halo, or for the
+  // comparison method the r(K+1) planes its steps reach down to
+  const int64_t below = d > 1 ? (P.resreu ? (int64_t)P.r * (P.K + 1) : halo) : 0;
   int64_t sp = 0;
-  for (int i = 0; i < d; ++i) sp = std::max<int64_t>(sp, P.bnd[i + 1] - P.bnd[i] + (i > 0 ? halo : 0));
+  for (int i = 0; i < d; ++i) sp = std::max<int64_t>(sp, P.bnd[i + 1] - P.bnd[i] + (i > 0 ? below : 0));
   P.lean = lean;
   if (lean) {
     const int n_launch = (P.K + P.k_on - 1) / P.k_on;
@@ -216,7 +288,9 @@ static bool chunks_ok(const Plan &P, int d) {
   // it must own at least that many (paper: halo space <= chunk)
   if (d < 1 || d > P.N) return false;
   if (d == 1) return true;
-  const int64_t halo = 2 * (int64_t)P.r * P.K;
+  // the comparison method shares r(s+1)..r(s-1) below level s: it needs the
+  // chunk to own r(K+1) planes so its level-K area stays inside it
+  const int64_t halo = P.resreu ? (int64_t)P.r * (P.K + 1) : 2 * (int64_t)P.r * P.K;
   for (int i = 0; i + 1 < d; ++i)
     if ((P.N * (i + 1)) / d - (P.N * i) / d < halo) return false;
   return true;
@@ -286,6 +360,18 @@ int make_plan(const so2dr_desc &D, Plan *P) {
   }
   P->budget = D.device_budget_bytes;
   P->adjoint = D.adjoint != 0;
+  if (D.method != SO2DR_METHOD_SO2DR && D.method != SO2DR_METHOD_RESREU) {
+    set_error("unknown method");
+    return SO2DR_E_INVALID;
+  }
+  P->resreu = D.method == SO2DR_METHOD_RESREU;
+  if (P->resreu) {
+    if (P->adjoint) {
+      set_error("the comparison method has no adjoint");
+      return SO2DR_E_UNSUPPORTED;
+    }
+    P->k_on = 1;  // its kernels can only advance one step (Sec. III)
+  }
   // ---- chunk count and slots
   if (D.n_chunks > 0) {
     if (!chunks_ok(*P, D.n_chunks)) {
@@ -299,7 +385,7 @@ int make_plan(const so2dr_desc &D, Plan *P) {
       --slots;
     }
     bool lean = false;
-    if (slots < 1 && !P->adjoint) {  // one buffer per slot instead of two
+    if (slots < 1 && !P->adjoint && !P->resreu) {  // one buffer per slot instead of two
       slots = want;
       while (slots >= 1 && plan_bytes(*P, D.n_chunks, slots, true) > P->budget) {
         if (D.n_slots > 0) { slots = 0; break; }
@@ -324,7 +410,7 @@ int make_plan(const so2dr_desc &D, Plan *P) {
       }
     }
     bool lean = false;
-    for (int d = 1; !chosen && !P->adjoint && d <= P->N; ++d) {  // lean layout as a last resort
+    for (int d = 1; !chosen && !P->adjoint && !P->resreu && d <= P->N; ++d) {  // lean as a last resort
       if (!chunks_ok(*P, d)) break;
       for (int slots = D.n_slots > 0 ? D.n_slots : std::min(3, d); slots >= 1; --slots)
         if (plan_bytes(*P, d, slots, true) <= P->budget) { chosen = d; chosen_slots = slots; lean = true; break; }

@@ -15,9 +15,10 @@
 // Dependencies are HIP events:
 //   * copy-in of chunk g waits copy-out of chunk g - n_slots (slot reuse);
 //   * compute of g waits its copy-in; copy-out of g waits its compute;
-//   * region sharing: the buffer operations of consecutive chunks (in
-//     round-major order) form a chain, so chunk i reads what chunk i-1 wrote
-//     before chunk i overwrites it (read, then write, as Algorithm 1 says);
+//   * region sharing: every access to a slot of the sharing buffer waits
+//     for the previous access to that slot, so chunk i reads what chunk i-1
+//     wrote before chunk i overwrites it (read, then write, as Algorithm 1
+//     says; per step for the comparison method);
 //   * host array, in place across rounds: round t+1's copy-in of chunk i
 //     waits round t's copy-out of chunks i and i+1, which write the planes it
 //     reads.  Within a round, chunk i's copy-out (which overwrites r k'
@@ -26,6 +27,7 @@
 // Nothing synchronises the device between rounds.
 #include <chrono>
 #include <cstring>
+#include <map>
 
 #include "launch.hpp"
 #include "plan.hpp"
@@ -157,19 +159,20 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
   const int nc = ns >= 3 ? ns - 2 : 1;
   auto s_comp = [&](int g) { return ns >= 3 ? P.streams[2 + g % nc] : P.streams[0]; };
   std::string msg;
-  int prev_rs = -1;  // sequence index of the last chunk whose RS ops were enqueued
-  int rs_open = -1;  // sequence index whose RS ops are being enqueued
+  // region-sharing buffer: every access to a pool slot waits for the previous
+  // access to that slot (write -> read -> write ... in schedule order)
+  size_t n_rs = 0;
+  for (const so2dr_op &op : ops) n_rs += (op.kind == SO2DR_OP_RS_READ || op.kind == SO2DR_OP_RS_WRITE);
+  rc = ensure_events(P.ev_rs, n_rs, hipEventDisableTiming);
+  if (rc) return rc;
+  std::map<int64_t, size_t> last_on_slot;
+  size_t rs_k = 0;
   int comp_g = -1;   // sequence index of the chunk whose compute ops are being enqueued
   for (size_t k = 0; k < ops.size(); ++k) {
     const so2dr_op &op = ops[k];
     const int g = op.round * P.d + op.chunk;
     const bool is_rs = op.kind == SO2DR_OP_RS_READ || op.kind == SO2DR_OP_RS_WRITE;
     hipStream_t s = op.kind == SO2DR_OP_H2D ? s_in : op.kind == SO2DR_OP_D2H ? s_out : s_comp(g);
-    if (rs_open >= 0 && !is_rs) {  // the chunk's RS group ended with the previous op
-      HIPCHK(hipEventRecord(P.ev_rs[rs_open], s_comp(rs_open)));
-      prev_rs = rs_open;
-      rs_open = -1;
-    }
     // cross-stream waits, enqueued before the op's timing start
     switch (op.kind) {
       case SO2DR_OP_H2D:
@@ -186,9 +189,9 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
           HIPCHK(hipStreamWaitEvent(s, P.ev_h2d[g], 0));
           comp_g = g;
         }
-        if (is_rs && rs_open < 0) {
-          if (prev_rs >= 0) HIPCHK(hipStreamWaitEvent(s, P.ev_rs[prev_rs], 0));
-          rs_open = g;
+        if (is_rs) {
+          auto it = last_on_slot.find(op.pool_off);
+          if (it != last_on_slot.end()) HIPCHK(hipStreamWaitEvent(s, P.ev_rs[it->second], 0));
         }
         break;
       case SO2DR_OP_D2H:
@@ -209,13 +212,16 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
       case SO2DR_OP_RS_READ:
       case SO2DR_OP_RS_WRITE: {
         const size_t n = (size_t)(op.z1 - op.z0) * pb;
+        char *pool = P.rs_pool() + (size_t)op.pool_off * pb;
         if (op.kind == SO2DR_OP_RS_READ) {
           char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
-          HIPCHK(hipMemcpyAsync(dst, P.rs_pool(), n, hipMemcpyDeviceToDevice, s));
+          HIPCHK(hipMemcpyAsync(dst, pool, n, hipMemcpyDeviceToDevice, s));
         } else {
           const char *src = P.slot_buf(op.slot, op.buf_in) + (size_t)(op.z0 - op.buf_z0) * pb;
-          HIPCHK(hipMemcpyAsync(P.rs_pool(), src, n, hipMemcpyDeviceToDevice, s));
+          HIPCHK(hipMemcpyAsync(pool, src, n, hipMemcpyDeviceToDevice, s));
         }
+        HIPCHK(hipEventRecord(P.ev_rs[rs_k], s));
+        last_on_slot[op.pool_off] = rs_k++;
         S.bytes_d2d += n;
         break;
       }

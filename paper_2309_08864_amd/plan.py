@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import DTYPES, OP_KINDS, SHAPES, check, lib
+from ._lib import DTYPES, METHODS, OP_KINDS, SHAPES, check, lib
 
 TORCH_DTYPES = {"f32": "float32", "f64": "float64", "bf16": "bfloat16", "f16": "float16"}
 
@@ -37,7 +37,7 @@ class Plan:
 
     def __init__(self, *, ndim, nx, ny, nz=1, shape="star", radius=1, weights, T, tb_depth=0,
                  n_chunks=0, k_on=0, n_slots=0, budget, storage="f32", bc=(0, 0, 0),
-                 adjoint=False):
+                 adjoint=False, method="so2dr"):
         self.storage = storage
         self.shape3 = (nz, ny, nx)
         self._T = T
@@ -53,6 +53,7 @@ class Plan:
         d.T, d.n_chunks, d.tb_depth, d.k_on, d.n_slots = T, n_chunks, tb_depth, k_on, n_slots
         d.device_budget_bytes = int(budget)
         d.adjoint = 1 if adjoint else 0
+        d.method = METHODS[method]
         h = ctypes.c_void_p()
         check(lib().so2dr_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

@@ -223,3 +223,22 @@ def test_lean_layout_bitwise(ndim, shape, r, storage):
     got, _, info = gpu_run(lean_kw, us)
     incore, _, _ = gpu_run(_kwargs(ndim, shape, r, w, T, T, 1, 1, storage=storage), us)
     assert torch.equal(got, incore)
+
+
+@pytest.mark.parametrize("ndim,shape,r", [(3, "star", 1), (3, "box", 1), (2, "box", 2)])
+def test_resreu_comparator_bitwise(ndim, shape, r):
+    """The comparison method (per-step sharing, single-step kernels) gives
+    the in-core bits too, with no redundant updates."""
+    rng = np.random.default_rng(91 + r)
+    offs = _offsets(ndim, shape, r)
+    w = _weights(offs, rng)
+    nx, ny, nz = _dims(ndim)
+    u0 = rng.random(np_shape(ndim, nx, ny, nz))
+    us = to_storage(u0, "f32")
+    T, K = 9, 4
+    d = 3 if r == 1 else 2
+    kw = dict(_kwargs(ndim, shape, r, w, T, K, d, 0), method="resreu")
+    got, st, info = gpu_run(kw, us, bind_streams=4)
+    assert info["method"] == 1 and st["cell_updates_done"] == st["cell_updates"]
+    incore, _, _ = gpu_run(_kwargs(ndim, shape, r, w, T, T, 1, 1), us)
+    assert torch.equal(got, incore)

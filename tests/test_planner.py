@@ -117,6 +117,34 @@ def test_paper_configuration_fits_and_counts():
     assert sum(1 for o in ops if o["kind"] == "KERNEL") == 4 * 4 * 40
 
 
+@pytest.mark.parametrize("ndim,shape,r,T,K,d", [(3, "star", 1, 10, 3, 4), (3, "box", 1, 7, 4, 3),
+                                                 (3, "star", 2, 6, 3, 2), (2, "box", 3, 5, 2, 3)])
+def test_resreu_schedule_matches_oracle(ndim, shape, r, T, K, d):
+    """The comparison method: per-step sharing through one buffer slot per
+    level, single-step kernels, no recomputation."""
+    nx, ny, N = 7, 5, 60
+    p, offs, w = _plan(ndim=ndim, nx=nx, ny=ny, nz=N, shape=shape, r=r, T=T, K=K, d=d, k_on=0,
+                       method="resreu")
+    info = p.info()
+    assert info["method"] == 1 and info["k_on"] == 1 and info["redundant_fraction"] == 0.0
+    ops = p.ops()
+    kp_first = min(K, T)
+    for i in range(1, d - 1):   # every step of an inner chunk reads then writes the buffer
+        kinds = [o["kind"] for o in ops if o["round"] == 0 and o["chunk"] == i]
+        assert kinds.count("RS_READ") == kp_first and kinds.count("RS_WRITE") == kp_first
+        assert kinds.count("KERNEL") == kp_first
+    rng = np.random.default_rng(T + K)
+    if ndim == 3:
+        u0 = rng.random((N, ny, nx))
+        ref = oracle.sweep(u0, offs, w, T)
+        host, lv = simulate(p, offs, w, u0, 0, 0, 3)
+    else:
+        u0 = rng.random((N, 1, nx))
+        ref = oracle.sweep(u0[:, 0, :], offs, w, T)[:, None, :]
+        host, lv = simulate(p, offs, w, u0, 0, 0, 2)
+    assert np.all(lv == T) and np.allclose(host, ref, rtol=1e-12, atol=1e-12)
+
+
 def test_lean_layout_for_the_2d_fp64_workload():
     """Four 256-row FP64 chunks need 4.19 MiB with two buffers per slot; the
     one-buffer layout fits the 4 MiB budget, and its schedule replays on the
@@ -243,16 +271,18 @@ def simulate(p, offs, w, u0, per_x=0, per_y=0, ndim=3):
             bufs[sl][op["buf_out"]][idx(z0, z1, b0)] = host[z0:z1]
             lvl[sl][op["buf_out"]][idx(z0, z1, b0)] = round_start
         elif kind == "RS_READ":
-            n = z1 - z0
-            assert np.all(pool_lvl[:n] == round_start), "stale region-sharing data"
-            bufs[sl][op["buf_out"]][idx(z0, z1, b0)] = pool[:n]
-            lvl[sl][op["buf_out"]][idx(z0, z1, b0)] = round_start
+            n, po = z1 - z0, op["pool_off"]
+            assert 0 <= po and po + n <= pool.shape[0]
+            assert np.all(pool_lvl[po:po + n] >= round_start), "stale region-sharing data"
+            bufs[sl][op["buf_out"]][idx(z0, z1, b0)] = pool[po:po + n]
+            lvl[sl][op["buf_out"]][idx(z0, z1, b0)] = pool_lvl[po:po + n]
         elif kind == "RS_WRITE":
-            n = z1 - z0
+            n, po = z1 - z0, op["pool_off"]
+            assert 0 <= po and po + n <= pool.shape[0]
             src = bufs[sl][op["buf_in"]]
-            assert np.all(lvl[sl][op["buf_in"]][idx(z0, z1, b0)] == round_start)
-            pool[:n] = src[idx(z0, z1, b0)]
-            pool_lvl[:n] = round_start
+            assert np.all(lvl[sl][op["buf_in"]][idx(z0, z1, b0)] >= round_start)
+            pool[po:po + n] = src[idx(z0, z1, b0)]
+            pool_lvl[po:po + n] = lvl[sl][op["buf_in"]][idx(z0, z1, b0)]
         elif kind == "KERNEL":
             L = op["levels"]
             s0 = round_start + op["level_in"]
