@@ -11,6 +11,8 @@ Contents:
     light-cone sub-box sweep for grids too large to sweep whole.
   * ``oracle.py`` - ctypes wrapper plus the stencil point sets (Fig. 1a of the
     paper: star = axis arms, box = full (2r+1)^dim cube).
+  * ``emulator.py`` - a bit-exact NumPy model of the library's documented
+    FP32 arithmetic (FMA chain order, per-step BF16/FP16 rounding).
 
 Every function below is pinned in ``tests/test_oracle_pins.py`` against
 mathematics that does not go through this code: exact rational arithmetic,
@@ -21,3 +23,4 @@ from .oracle import (  # noqa: F401
     stencil_offsets, sweep, transpose_step, adjoint, sweep_box, build, lib_path,
     extract_window, sweep_box_from_field, sweep_box_window, reach_of,
 )
+from . import emulator  # noqa: F401

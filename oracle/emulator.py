@@ -1,0 +1,111 @@
+"""Bit-exact CPU model of the library's reduced-precision arithmetic.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  The C interface
+promises a specific arithmetic: every cell's sum is a chain of fused
+multiply-adds in FP32, starting from +0 and running over the stencil points
+in lexicographic (dz, dy, dx) order, with FP32-rounded weights; BF16 / FP16
+storage rounds the sum to nearest-even after every step.  This module models
+exactly that in NumPy, so GPU results can be compared bit for bit.  It shares
+nothing with the HIP code: it is written from the interface's description.
+
+FP32 fused multiply-add, exactly: for float32 a, b, c the product a*b is
+exact in float64 (48 significant bits); TwoSum gives s + e == a*b + c exactly
+with s, e float64; rounding s to float32 gives the correct result unless s is
+exactly halfway between two float32 values and e != 0, in which case the
+exact value lies on e's side of the midpoint.
+"""
+import numpy as np
+
+
+def _two_sum(a, b):
+    s = a + b
+    bp = s - a
+    ap = s - bp
+    return s, (a - ap) + (b - bp)
+
+
+def fma32(a, b, c):
+    """Correctly rounded float32 fma(a, b, c), elementwise."""
+    a = np.asarray(a, np.float32).astype(np.float64)
+    b = np.asarray(b, np.float32).astype(np.float64)
+    c = np.asarray(c, np.float32).astype(np.float64)
+    p = a * b
+    s, e = _two_sum(p, c)
+    r = s.astype(np.float32)
+    # s is an exact float32 midpoint iff it is not a float32 but s +- half an
+    # ulp are; detect it as: rounding down and up of s straddle it equally
+    lo = np.nextafter(r, np.float32(-np.inf)).astype(np.float64)
+    hi = np.nextafter(r, np.float32(np.inf)).astype(np.float64)
+    r64 = r.astype(np.float64)
+    mid_lo = (r64 + lo) / 2.0      # exact in float64
+    mid_hi = (r64 + hi) / 2.0
+    at_lo = (s == mid_lo) & (e != 0)
+    at_hi = (s == mid_hi) & (e != 0)
+    out = r.copy()
+    # s halfway below r (r was chosen by ties-to-even): exact value is below s
+    # when e < 0, so the right answer is the lower neighbour
+    out = np.where(at_lo & (e < 0), lo.astype(np.float32), out)
+    out = np.where(at_hi & (e > 0), hi.astype(np.float32), out)
+    # s halfway and r rounded away from the exact side: when s == mid_lo and
+    # e > 0 the exact value is above the midpoint, so r (above) is right; when
+    # s == mid_hi and e < 0, r (below) is right
+    return out
+
+
+def round_bf16(x):
+    """float32 -> nearest-even bfloat16, returned as float32 values."""
+    x = np.ascontiguousarray(x, np.float32)
+    bits = x.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> 16) & 1
+    rb = ((bits + 0x7FFF + lsb) >> 16) << 16
+    return rb.astype(np.uint32).view(np.float32)
+
+
+def round_f16(x):
+    """float32 -> nearest-even float16, returned as float32 values."""
+    return np.asarray(x, np.float32).astype(np.float16).astype(np.float32)
+
+
+_ROUND = {"f32": lambda v: v, "bf16": round_bf16, "f16": round_f16}
+
+
+def _shifted(u, o, periodic):
+    """v(x) = u(x + o) with zero (Dirichlet) or wrapped (periodic) ghosts;
+    u is (z, y, x), o is (dz, dy, dx), periodic is per axis (x, y, z)."""
+    v = u
+    for axis, d in enumerate(o):
+        if d == 0:
+            continue
+        if periodic[2 - axis]:
+            v = np.roll(v, -d, axis=axis)
+        else:
+            n = v.shape[axis]
+            w = np.zeros_like(v)
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            if abs(d) < n:
+                if d > 0:
+                    src[axis], dst[axis] = slice(d, n), slice(0, n - d)
+                else:
+                    src[axis], dst[axis] = slice(0, n + d), slice(-d, n)
+                w[tuple(dst)] = v[tuple(src)]
+            v = w
+    return v
+
+
+def sweep_bits(u0, offsets, weights, T, storage="f32", periodic=(0, 0, 0)):
+    """T steps of the FP32-FMA sweep with per-step rounding to `storage`
+    (f32, bf16 or f16).  u0 holds values already representable in the
+    storage type; returns float32 values.  offsets: (dz, dy, dx) in the order
+    the sums run (lexicographic); a 2D field is (y, x) with dz == 0."""
+    two_d = np.asarray(u0).ndim == 2
+    u = np.asarray(u0, np.float32)
+    u = u[None] if two_d else u
+    w32 = np.asarray(weights, np.float64).astype(np.float32)
+    rnd = _ROUND[storage]
+    for _ in range(T):
+        acc = np.zeros_like(u)           # +0
+        for o, wk in zip(offsets, w32):
+            acc = fma32(wk, _shifted(u, o, periodic), acc)
+        u = rnd(acc)
+    return u[0] if two_d else u
