@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--tb-depth", type=int, default=0)
     ap.add_argument("--chunks", type=int, default=0)
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--method", default="so2dr", choices=["so2dr", "resreu"],
+                    help="resreu: the paper's comparison code (per-step sharing, one-step kernels)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-planes", type=int, default=0)
     ap.add_argument("--compare-storage", default=None,
@@ -129,7 +131,8 @@ def main():
     d = args.chunks or wl.n_chunks
     plan = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
                 weights=list(w), T=wl.T, tb_depth=K, n_chunks=d, k_on=args.k_on,
-                n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic)
+                n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic,
+                method=args.method)
     info = plan.info()
     plan.bind()
     plan.set_timing(True)
@@ -181,16 +184,17 @@ def main():
             "workload": f"{wl.name}: {wl.ndim}D {wl.shape} r={wl.radius} "
                         f"{wl.nx}x{wl.ny}x{wl.nz} {storage}, T={wl.T}, tb_depth={info['tb_depth']}, "
                         f"{info['n_chunks']} chunks, {info['n_slots']} slots, k_on={info['k_on']}, "
-                        f"budget {wl.budget / 2**30:g} GiB",
+                        f"budget {wl.budget / 2**30:g} GiB, method {args.method}",
             "cells": cells, "T": wl.T, "tb_depth": info["tb_depth"], "n_chunks": info["n_chunks"],
             "k_on": info["k_on"], "n_slots": info["n_slots"], "budget_bytes": wl.budget,
             "workspace_bytes": info["workspace_bytes"],
             "redundant_fraction": round(info["redundant_fraction"], 4),
+            "method": args.method, "lean": info["lean"],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
-            "kernel": "tb_kernel (fused-step stencil kernel)",
+            "kernel": "fused-step stencil kernel (col3d_kernel for 3D, tb_kernel for 2D)",
             "launches": tot["kernel_launches"],
             "avg_launch_ms": round(tot["kernel_ms"] / max(1, tot["kernel_launches"]), 4),
             "alg_bytes_per_launch": tot["kernel_alg_bytes"] // max(1, tot["kernel_launches"]),

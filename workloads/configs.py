@@ -58,3 +58,20 @@ CONFIGS = {
         notes="adjoint of the 7-point sweep, checkpoints every 16 steps",
         extra={"ckpt_every": 16, "target_seed": 50}),
 }
+
+
+# The paper's benchmark family (Table III): box2d{x}r, x = 1..4, FP32, out of
+# core at 38400^2 (two arrays = 11.0 GB), 640 steps, 4 chunks, S_TB chosen per
+# radius as in Sec. V-B (160, 160, 80, 40), on a 10 GB device.  The stencil
+# coefficients of the paper's generator are not given, so the weights are
+# random positive values normalised to 1 (seeded); input U[0, 1).
+PAPER_S_TB = {1: 160, 2: 160, 3: 80, 4: 40}
+for _r in (1, 2, 3, 4):
+    CONFIGS[f"paper_box2d{_r}r"] = Workload(
+        f"paper_box2d{_r}r", 2, 38400, 38400, 1, "box", _r, T=640, tb_depth=PAPER_S_TB[_r],
+        n_chunks=4, budget=10 * 10 ** 9, seed=100 + _r, init="uniform", weights="random_box",
+        notes="paper out-of-core dataset (Table III), S_TB as in Sec. V-B")
+    CONFIGS[f"paper_box2d{_r}r_incore"] = Workload(
+        f"paper_box2d{_r}r_incore", 2, 12800, 12800, 1, "box", _r, T=640, tb_depth=PAPER_S_TB[_r],
+        n_chunks=4, budget=10 * 10 ** 9, seed=200 + _r, init="uniform", weights="random_box",
+        notes="paper in-core dataset (Table III), chunked like the out-of-core runs")
