@@ -103,10 +103,10 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   return 0;
 }
 
-template <typename T, bool BOX, int R, int KL>
+template <typename T, bool BOX, int R, int KL, int NW = SO2DR_STAR_NW, int M = SO2DR_STAR_M,
+          int VX = SO2DR_STAR_VX, int HB = SO2DR_STAR_HB>
 int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
-  constexpr int NW = SO2DR_STAR_NW, M = SO2DR_STAR_M, VX = SO2DR_STAR_VX, HB = SO2DR_STAR_HB;
   using G = StarTile<R, KL, NW, M, VX>;
   using S = Stencil<3, BOX, R>;
   if (p.npts != S::npts()) {
@@ -150,15 +150,17 @@ int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) 
   return 0;
 }
 
-// 3D stencils go to the register-column kernel when its tile and LDS fit,
-// 2D ones to the LDS-plane kernel; both compute the same bits.
+// Kernel choice per depth, from measurements on MI355X (one launch over a
+// 2048x1024x80 FP32 chunk): single-step launches of 3D stencils stream best
+// with the register-column kernel in 1 KiB rows (16 waves x 2 rows, one halo
+// buffer); fused launches run best in the LDS-plane kernel.  Both compute
+// the same bits.
 template <typename T, int NDIM, bool BOX, int R, int KL>
 int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
-  constexpr size_t star_lds =
-      sizeof(typename Store<T>::A) * KL * SO2DR_STAR_HB * SO2DR_STAR_NW * 2 * R * 64 * SO2DR_STAR_VX;
-  if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && (KL * R * 2 < SO2DR_STAR_NW * SO2DR_STAR_M) &&
-                star_lds <= 65536)
-    return launch_col_one<T, BOX, R, KL>(p, s, msg);
+  constexpr int NW = 16, M = 2, VX = 4, HB = 1;
+  constexpr size_t col_lds = sizeof(typename Store<T>::A) * KL * HB * NW * 2 * R * 64 * VX;
+  if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL == 1 && col_lds <= 65536)
+    return launch_col_one<T, BOX, R, KL, NW, M, VX, HB>(p, s, msg);
   else
     return launch_one<T, NDIM, BOX, R, KL>(p, s, msg);
 }

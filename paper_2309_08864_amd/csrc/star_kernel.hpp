@@ -97,6 +97,23 @@ template <typename H16, int VX> struct VecIOHalf {
 };
 template <int VX> struct VecIO<__hip_bfloat16, VX> : VecIOHalf<__hip_bfloat16, VX> {};
 template <int VX> struct VecIO<__half, VX> : VecIOHalf<__half, VX> {};
+// one cell per lane: plain scalar accesses
+template <> struct VecIO<float, 1> {
+  static __device__ __forceinline__ void load(const float *p, float *v) { v[0] = *p; }
+  static __device__ __forceinline__ void store(float *p, const float *v) { *p = v[0]; }
+};
+template <> struct VecIO<double, 1> {
+  static __device__ __forceinline__ void load(const double *p, double *v) { v[0] = *p; }
+  static __device__ __forceinline__ void store(double *p, const double *v) { *p = v[0]; }
+};
+template <> struct VecIO<__hip_bfloat16, 1> {
+  static __device__ __forceinline__ void load(const __hip_bfloat16 *p, float *v) { v[0] = Store<__hip_bfloat16>::load(p); }
+  static __device__ __forceinline__ void store(__hip_bfloat16 *p, const float *v) { Store<__hip_bfloat16>::store(p, v[0]); }
+};
+template <> struct VecIO<__half, 1> {
+  static __device__ __forceinline__ void load(const __half *p, float *v) { v[0] = Store<__half>::load(p); }
+  static __device__ __forceinline__ void store(__half *p, const float *v) { Store<__half>::store(p, v[0]); }
+};
 
 template <int R, int KL, int NW, int M, int VX_>
 struct StarTile {
@@ -105,7 +122,7 @@ struct StarTile {
   static constexpr int HX = (KL * R + VX - 1) / VX * VX;  // x halo, whole lanes
   static constexpr int HY = KL * R;
   static constexpr int OX = TX - 2 * HX, OY = TY - 2 * HY;
-  static_assert(M >= R && R <= VX && OX > 0 && OY > 0, "tile too small for this depth");
+  static_assert(M >= R && R <= 2 * VX && OX > 0 && OY > 0, "tile too small for this depth");
 };
 
 template <typename T, bool BOX, int R, int KL, int NW, int M, int VX_, int HB>
@@ -266,10 +283,14 @@ __global__ __launch_bounds__(NW * 64) void col3d_kernel(const TbArgs<typename St
       for (int i = 0; i < M + 2 * R; ++i) {
 #pragma unroll
         for (int j = 0; j < VX; ++j) row[i][R + j] = col[i][j];
+        // the cell k to the left of this lane's first cell sits in lane
+        // -ceil(k/VX) at element VX*ceil(k/VX) - k; symmetrically on the right
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          row[i][R - 1 - r] = dpp_f<kDppWaveShr1>(col[i][VX - 1 - r]);
-          row[i][R + VX + r] = dpp_f<kDppWaveShl1>(col[i][r]);
+        for (int k = 1; k <= R; ++k) {
+          const int sh = (k + VX - 1) / VX;
+          const A lv = col[i][VX * sh - k], rv = col[i][k - 1 - VX * (sh - 1)];
+          row[i][R - k] = sh == 1 ? dpp_f<kDppWaveShr1>(lv) : dpp_f<kDppWaveShr1>(dpp_f<kDppWaveShr1>(lv));
+          row[i][R + VX - 1 + k] = sh == 1 ? dpp_f<kDppWaveShl1>(rv) : dpp_f<kDppWaveShl1>(dpp_f<kDppWaveShl1>(rv));
         }
       }
 #pragma unroll

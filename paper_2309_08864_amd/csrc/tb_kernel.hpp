@@ -36,7 +36,7 @@
 #include <stdint.h>
 
 #ifndef SO2DR_XCD_REMAP
-#define SO2DR_XCD_REMAP 0
+#define SO2DR_XCD_REMAP 1
 #endif
 #ifndef SO2DR_PREFETCH2
 #define SO2DR_PREFETCH2 0
@@ -92,11 +92,20 @@ template <> struct Store<__hip_bfloat16> {
   static __device__ __forceinline__ void store(__hip_bfloat16 *p, float v) { *p = __float2bfloat16(v); }
   static __device__ __forceinline__ float round(float v) { return __bfloat162float(__float2bfloat16(v)); }
 };
+// FP32 -> FP16 happens on a value pinned in a register first: otherwise the
+// compiler may fuse the last FMA of a sum with the conversion into one
+// mixed-precision instruction that rounds the exact value once, instead of
+// the documented FP32 rounding followed by FP16 rounding -- and may do so in
+// some kernels but not others, which would break schedule independence.
+__device__ __forceinline__ float pin_f32(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 template <> struct Store<__half> {
   using A = float;
   static __device__ __forceinline__ float load(const __half *p) { return __half2float(*p); }
-  static __device__ __forceinline__ void store(__half *p, float v) { *p = __float2half(v); }
-  static __device__ __forceinline__ float round(float v) { return __half2float(__float2half(v)); }
+  static __device__ __forceinline__ void store(__half *p, float v) { *p = __float2half(pin_f32(v)); }
+  static __device__ __forceinline__ float round(float v) { return __half2float(__float2half(pin_f32(v))); }
 };
 
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
