@@ -151,16 +151,24 @@ int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) 
 }
 
 // Kernel choice per depth, from measurements on MI355X (one launch over a
-// 2048x1024x80 FP32 chunk): single-step launches of 3D stencils stream best
-// with the register-column kernel in 1 KiB rows (16 waves x 2 rows, one halo
-// buffer); fused launches run best in the LDS-plane kernel.  Both compute
-// the same bits.
+// 2048x1024x80 FP32 chunk, 7-point star / 27-point box):
+//   * single-step launches stream best with the register-column kernel in
+//     1 KiB rows (4 cells per lane, 16 waves x 2 rows, one halo buffer):
+//     4.35 TB/s against 3.6 for the LDS-plane kernel;
+//   * fused launches run best with one cell per lane and 8 rows per wave
+//     (4 waves, double-buffered halo): 1.1 T updates/s at 3 levels against
+//     0.78 for the LDS-plane kernel, whose registers spill less at depth.
+// The LDS-plane kernel serves 2D grids and whatever does not fit.  All of
+// them compute the same bits.
 template <typename T, int NDIM, bool BOX, int R, int KL>
 int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
-  constexpr int NW = 16, M = 2, VX = 4, HB = 1;
-  constexpr size_t col_lds = sizeof(typename Store<T>::A) * KL * HB * NW * 2 * R * 64 * VX;
-  if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL == 1 && col_lds <= 65536)
-    return launch_col_one<T, BOX, R, KL, NW, M, VX, HB>(p, s, msg);
+  using A = typename Store<T>::A;
+  constexpr size_t lds1 = sizeof(A) * KL * 1 * 16 * 2 * R * 64 * 4;
+  constexpr size_t ldsn = sizeof(A) * KL * 2 * 4 * 2 * R * 64 * 1;
+  if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL == 1 && lds1 <= 65536)
+    return launch_col_one<T, BOX, R, KL, 16, 2, 4, 1>(p, s, msg);
+  else if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL >= 2 && 2 * KL * R < 32 && ldsn <= 65536)
+    return launch_col_one<T, BOX, R, KL, 4, 8, 1, 2>(p, s, msg);
   else
     return launch_one<T, NDIM, BOX, R, KL>(p, s, msg);
 }

@@ -255,7 +255,7 @@ def test_bit_exact_vs_arithmetic_model(storage, ndim, shape, r):
     rng = np.random.default_rng(101 + r + 7 * ndim)
     offs = _offsets(ndim, shape, r)
     w = fp32_weights(_weights(offs, rng, positive=False))
-    nx, ny, nz = (300, 30, 17) if ndim == 3 else (1100, 23, 1)
+    nx, ny, nz = (300, 30, 17) if ndim == 3 else (1100, 61, 1)   # chunks own >= 2 r K planes
     per = (1, 0, 0) if shape == "box" else (0, 0, 0)
     u0 = rng.random(np_shape(ndim, nx, ny, nz))
     us = to_storage(u0, storage)
