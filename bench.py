@@ -25,6 +25,34 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, vendor figure
 LINK_PEAK_GBPS = 2 * 63.0       # PCIe 5.0 x16, both directions, vendor figure
 
 
+def measured_traffic(config_key):
+    """HBM bytes per launch of the fused kernel, from a committed hardware
+    counter summary under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a
+    copy of known size), or None when no summary covers this configuration
+    or the kernel sources changed after the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        kv = {}
+        for line in open(path):
+            line = line.strip()
+            if "=" in line and " " not in line:
+                k, v = line.split("=", 1)
+                kv[k] = v
+        if kv.get("config_key") != config_key:
+            continue
+        h = hashlib.sha256()
+        for name in kv.get("kernel_sources", "").split(","):
+            src = os.path.join(ROOT, "paper_2309_08864_amd", "csrc", name)
+            if not os.path.isfile(src):
+                return None
+            h.update(open(src, "rb").read())
+        if h.hexdigest() != kv.get("kernel_sources_sha256"):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +195,8 @@ def main():
     value = cells * wl.T * args.steps / elapsed / 1e9
     achieved = tot["kernel_alg_bytes"] / (tot["kernel_ms"] / 1e3) / 1e9 if tot["kernel_ms"] else 0.0
     link_bytes = tot["bytes_h2d"] + tot["bytes_d2h"]
+    traffic = measured_traffic(f"{wl.name}/{storage}/K{info['tb_depth']}/d{info['n_chunks']}/"
+                               f"k_on{info['k_on']}/{args.method}")
     res = {
         "metric": "GCell-updates/s out-of-core",
         "value": round(value, 3),
@@ -193,7 +223,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": round(traffic) if traffic else None,
             "kernel": "fused-step stencil kernel (col3d_kernel for 3D, tb_kernel for 2D)",
             "launches": tot["kernel_launches"],
             "avg_launch_ms": round(tot["kernel_ms"] / max(1, tot["kernel_launches"]), 4),
