@@ -56,7 +56,7 @@ def measured_traffic(config_key):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2_3d7pt")
     ap.add_argument("--storage", default=None)
@@ -131,6 +131,71 @@ def cpu_baseline(wl, offs, w, planes):
                       f"(FP64, {dt:.1f} s)"}
 
 
+def bench_adjoint(args, wl, w):
+    """Times the whole gradient (forward with host checkpoints, loss, reverse
+    sweep with recompute, weight gradients) of 1/2 ||u_T - y||^2; the target
+    y is the same sweep with perturbed weights.  value = nx ny nz T / wall."""
+    import torch
+    import workloads
+    from paper_2309_08864_amd import Plan
+    from paper_2309_08864_amd.plan import adjoint_buffers_needed
+    c = wl.extra["ckpt_every"]
+    shape = (wl.nz, wl.ny, wl.nx)
+    base = dict(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
+                T=wl.T, tb_depth=args.tb_depth or wl.tb_depth, n_chunks=args.chunks or wl.n_chunks,
+                k_on=args.k_on, n_slots=args.slots, budget=wl.budget, bc=wl.periodic)
+    u0 = draw_field(wl, torch.float32)
+    wt = workloads.fp32_rounded(workloads.perturbed(w, wl.extra["target_seed"]))
+    y = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+    pt = Plan(weights=list(wt), **base).bind()
+    t0 = time.perf_counter()
+    pt.run_steps(u0, y, wl.T)
+    t_fwd = time.perf_counter() - t0
+    pt.close()
+    plan = Plan(weights=list(w), adjoint=True, **base).bind()
+    info = plan.info()
+    ckpt = [torch.empty(shape, dtype=torch.float32, pin_memory=True)
+            for _ in range(adjoint_buffers_needed(wl.T, info["tb_depth"], c))]
+    g = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+    print(f"# adjoint plan {info}; {len(ckpt)} host checkpoint fields; forward {t_fwd:.2f} s",
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        plan.adjoint(u0, y, c, ckpt=ckpt, grad_u0=g)
+        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    link = 0
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        loss, _, gw, st = plan.adjoint(u0, y, c, ckpt=ckpt, grad_u0=g)
+        link += st["bytes_h2d"] + st["bytes_d2h"]
+        print(f"# step {i}: {st['wall_ms']:.1f} ms, loss {loss:.6e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    plan.close()
+    value = wl.cells * wl.T * args.steps / elapsed / 1e9
+    res = {
+        "metric": "GCell-updates/s out-of-core (gradient of the sweep)",
+        "value": round(value, 3), "unit": "GCell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: gradient of 1/2||u_T - y||^2 through the {wl.ndim}D "
+                        f"{wl.shape} r={wl.radius} sweep, {wl.nx}x{wl.ny}x{wl.nz} f32, T={wl.T}, "
+                        f"checkpoints every {c} steps, tb_depth={info['tb_depth']}, "
+                        f"{info['n_chunks']} chunks, k_on={info['k_on']}, "
+                        f"budget {wl.budget / 2**30:g} GiB",
+            "cells": wl.cells, "T": wl.T, "workspace_bytes": info["workspace_bytes"],
+            "host_checkpoint_fields": len(ckpt)},
+        "forward_GCells": round(wl.cells * wl.T / t_fwd / 1e9, 3),
+        "gradient_over_forward_time": round(elapsed / args.steps / t_fwd, 3),
+        "link": {"achieved_GBps": round(link / elapsed / 1e9, 2), "peak_GBps": LINK_PEAK_GBPS},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -155,6 +220,8 @@ def main():
     w = weights_for(wl, offs)
     if storage != "f64":
         w = workloads.fp32_rounded(w)
+    if wl.extra.get("ckpt_every"):
+        return bench_adjoint(args, wl, w)
     K = args.tb_depth or wl.tb_depth
     d = args.chunks or wl.n_chunks
     plan = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,

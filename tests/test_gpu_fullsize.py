@@ -23,6 +23,17 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 WL = workloads.CONFIGS
 
 
+@pytest.fixture(autouse=True)
+def _release_pinned():
+    """Each test pins tens of GiB of host memory; hand it back afterwards
+    instead of leaving it in torch's pinned-block cache."""
+    yield
+    import gc
+    gc.collect()
+    if hasattr(torch._C, "_host_emptyCache"):
+        torch._C._host_emptyCache()
+
+
 def _log(msg):
     print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
 
