@@ -5,11 +5,15 @@
 #include <string>
 
 #include "launch.hpp"
+#include "march_kernel.hpp"
 #include "star_kernel.hpp"
 #include "tb_kernel.hpp"
 
 #ifndef SO2DR_STAR_KERNEL
 #define SO2DR_STAR_KERNEL 1
+#endif
+#ifndef SO2DR_MARCH_KERNEL
+#define SO2DR_MARCH_KERNEL 1
 #endif
 #ifndef SO2DR_STAR_NW
 #define SO2DR_STAR_NW 8
@@ -150,19 +154,97 @@ int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) 
   return 0;
 }
 
+// Whether the march kernel's layout fits this launch: whole VX-cell vectors
+// per row, 32-bit byte offsets within a plane, 32-bit plane indices.
+template <typename T, int VX>
+inline bool march_fits(const LaunchParams &p) {
+  return p.nx % VX == 0 && (uint64_t)p.plane * sizeof(T) < ((uint64_t)1 << 32) &&
+         p.n_axis < ((int64_t)1 << 30) && p.in_lo > -((int64_t)1 << 29) && p.buf_z0 > -((int64_t)1 << 29) &&
+         p.out_z0 > -((int64_t)1 << 29) && p.in_lo < p.in_hi;
+}
+
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1>
+int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
+  using A = typename Store<T>::A;
+  using G = StarTile<R, KL, NW, M, VX>;
+  using S = Stencil<3, BOX, R>;
+  if (p.npts != S::npts()) {
+    if (msg) *msg = "weight count does not match the stencil";
+    return -1;
+  }
+  if (!march_fits<T, VX>(p)) {
+    if (msg) *msg = "launch does not fit the march kernel's layout";
+    return -1;
+  }
+  TbArgs<A> a{};
+  a.in = p.in;
+  a.out = p.out;
+  a.buf_z0 = p.buf_z0;
+  a.out_z0 = p.out_z0;
+  a.plane = p.plane;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.per_x = p.per_x;
+  a.per_y = p.per_y;
+  a.n_axis = p.n_axis;
+  a.in_lo = p.in_lo;
+  a.in_hi = p.in_hi;
+  a.out_lo = p.out_lo;
+  a.out_hi = p.out_hi;
+  for (int i = 0; i < S::npts(); ++i) a.w.w[i] = (A)p.weights[i];
+  a.ntx = (int)((p.nx + G::OX - 1) / G::OX);
+  a.nty = (int)((p.ny + G::OY - 1) / G::OY);
+  const int64_t span = p.out_hi - p.out_lo;
+  if (span <= 0) return 0;
+  plan_segments(span, (int64_t)a.ntx * a.nty, &a.zseg, &a.nseg);
+  const int64_t nwg = (int64_t)a.ntx * a.nty * a.nseg;
+  if (nwg > 0x7fffffff) {
+    if (msg) *msg = "grid too large for one launch";
+    return -1;
+  }
+  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  hipLaunchKernelGGL((march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE>), dim3((unsigned)grid), dim3(NW * 64), 0,
+                     stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (msg) *msg = std::string("kernel launch: ") + hipGetErrorString(e);
+    return -5;
+  }
+  return 0;
+}
+
+// Bytes of the march kernel's halo buffers.
+template <typename A, int KL, int NW, int R, int VX, int HB>
+constexpr size_t march_lds() {
+  return sizeof(A) * KL * HB * NW * 2 * R * 64 * VX;
+}
+
 // Kernel choice per depth, from measurements on MI355X (one launch over a
-// 2048x1024x80 FP32 chunk, 7-point star / 27-point box):
-//   * single-step launches stream best with the register-column kernel in
-//     1 KiB rows (4 cells per lane, 16 waves x 2 rows, one halo buffer):
-//     4.35 TB/s against 3.6 for the LDS-plane kernel;
-//   * fused launches run best with one cell per lane and 8 rows per wave
-//     (4 waves, double-buffered halo): 1.1 T updates/s at 3 levels against
-//     0.78 for the LDS-plane kernel, whose registers spill less at depth.
-// The LDS-plane kernel serves 2D grids and whatever does not fit.  All of
-// them compute the same bits.
+// 2048x1024x80 FP32 chunk; all variants give identical bits):
+//   * single-step launches, and two fused steps of the radius-1 star, run
+//     best with 1 KiB rows (4 cells per lane, 16 waves of 2 rows):
+//     0.31-0.32 ms, 4.1-4.3 TB/s;
+//   * deeper fusion, the 13-point star and the 27-point box run best with
+//     512-byte rows (2 cells per lane, 8 waves of 4 rows, two workgroups per
+//     CU): 7-point at 3 levels 1.22 T updates/s (0.38 ms), 27-point at 2
+//     levels 0.68 T updates/s;
+//   * grids whose row length is not a multiple of the cells per lane fall
+//     back to the register-column kernel, 2D grids and whatever does not fit
+//     to the LDS-plane kernel.
 template <typename T, int NDIM, bool BOX, int R, int KL>
 int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
   using A = typename Store<T>::A;
+  constexpr size_t kLdsMax = 160 * 1024;
+  if constexpr (NDIM == 3 && SO2DR_MARCH_KERNEL) {
+    constexpr bool wide = (KL == 1 || (KL == 2 && !BOX && R == 1)) && march_lds<A, KL, 16, R, 4, 2>() <= kLdsMax;
+    constexpr int HB = march_lds<A, KL, 8, R, 2, 2>() <= 65536 ? 2 : 1;
+    if constexpr (wide) {
+      if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 16, 2, 4, 2, 2>(p, s, msg);
+    } else if constexpr (march_lds<A, KL, 8, R, 2, HB>() <= kLdsMax && 2 * ((KL * R + 1) / 2) < 32 &&
+                         4 >= R && 32 > 2 * KL * R) {
+      if (march_fits<T, 2>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 2, HB, 2>(p, s, msg);
+    }
+  }
   constexpr size_t lds1 = sizeof(A) * KL * 1 * 16 * 2 * R * 64 * 4;
   constexpr size_t ldsn = sizeof(A) * KL * 2 * 4 * 2 * R * 64 * 1;
   if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL == 1 && lds1 <= 65536)

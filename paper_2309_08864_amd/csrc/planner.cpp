@@ -355,9 +355,9 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     }
     P->k_on = std::min(D.k_on, P->K);
   } else {
-    // measured best update rate per launch: 3 fused levels for radius-1 3D
-    // stencils, 2 for radius 2, 4 for 2D rows
-    const int pref = P->ndim == 2 ? 4 : (P->r == 1 ? 3 : 2);
+    // measured best update rate per launch: 3 fused levels for the 7-point
+    // star, 2 for the 13-point star and the 27-point box, 4 for 2D rows
+    const int pref = P->ndim == 2 ? 4 : (P->r == 1 && P->shape == SO2DR_STAR ? 3 : 2);
     P->k_on = std::max(1, std::min({pref, P->max_k_on, P->K}));
   }
   P->budget = D.device_budget_bytes;

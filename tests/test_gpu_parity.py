@@ -1,8 +1,10 @@
 """GPU parity: the HIP path against the FP64 oracle, and out-of-core runs
 against the in-core run of the same storage type (bit for bit).
 
-Sizes span several xy tiles (64-wide, 16/32-high in 3D; 1024/512-wide rows
-in 2D) with ragged tails, several chunks and rounds with remainders."""
+Sizes span several xy tiles (256- or 128-wide, 32-high in 3D; 1024/512-wide
+rows in 2D) with ragged tails, several chunks and rounds with remainders.
+3D rows whose length is not a multiple of the cells a lane owns take the
+register-column kernel instead; a test of its own covers that path."""
 import numpy as np
 import pytest
 import torch
@@ -21,8 +23,9 @@ def _weights(offs, rng, positive=True):
 
 
 def _dims(ndim):
-    # 3D: 2 x-tiles, 2-3 y-tiles, ragged; 2D: 2 row tiles, ragged
-    return (1100, 57, 1) if ndim == 2 else (70, 37, 29)
+    # 3D: 2-3 x-tiles (248 / 120 output columns per tile), 2 y-tiles, ragged;
+    # 2D: 2 row tiles, ragged
+    return (1100, 57, 1) if ndim == 2 else (264, 37, 29)
 
 
 def _kwargs(ndim, shape, r, w, T, K, d, k_on, storage="f32", bc=(0, 0, 0), slots=0,
@@ -275,3 +278,28 @@ def test_bit_exact_vs_arithmetic_model(storage, ndim, shape, r):
     diff = int(np.sum(g.view(np.uint32) != model.view(np.uint32)))
     print(f"[{storage} {ndim}D {shape} r={r}] cells differing from the model: {diff}", flush=True)
     assert diff == 0
+
+
+@pytest.mark.parametrize("shape,r", [("star", 1), ("star", 2), ("box", 1)])
+def test_f32_row_length_fallback_kernel(shape, r):
+    """nx = 70 is not a multiple of 4 (nor of the 128-cell tile): the launcher
+    takes the register-column kernel; every fused depth against the oracle
+    and bit for bit against the in-core run."""
+    rng = np.random.default_rng(40 + r)
+    offs = _offsets(3, shape, r)
+    w = _weights(offs, rng)
+    nx, ny, nz = 70, 37, 29
+    u0 = rng.random((nz, ny, nx))
+    T, K = 7, 3
+    d = max(2, min(4, nz // (2 * r * K)))
+    us = to_storage(u0, "f32")
+    ref = oracle.sweep(us.double().numpy(), offs, fp32_weights(w), T)
+    base = dict(ndim=3, nx=nx, ny=ny, nz=nz, shape=shape, radius=r, weights=list(w), T=T,
+                budget=4 << 30, storage="f32")
+    incore, _, _ = gpu_run(dict(base, tb_depth=T, n_chunks=1, k_on=1), us)
+    assert rel_l2(incore.double().numpy(), ref) <= 1e-5
+    from paper_2309_08864_amd import Plan
+    maxk = Plan(**dict(base, tb_depth=K, n_chunks=d)).info()["max_k_on"]
+    for k_on in range(1, min(3, maxk) + 1):
+        got, _, _ = gpu_run(dict(base, tb_depth=K, n_chunks=d, k_on=k_on), us)
+        assert torch.equal(got, incore), (shape, r, k_on)
