@@ -5,6 +5,7 @@
 #include <string>
 
 #include "launch.hpp"
+#include "march2d_kernel.hpp"
 #include "march_kernel.hpp"
 #include "star_kernel.hpp"
 #include "tb_kernel.hpp"
@@ -213,6 +214,57 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
   return 0;
 }
 
+template <typename T, bool BOX, int R, int KL, int VX, int PF, bool ROT>
+int launch_march2d_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
+  using A = typename Store<T>::A;
+  using G = RowTile<R, KL, VX>;
+  using S = Stencil<2, BOX, R>;
+  if (p.npts != S::npts()) {
+    if (msg) *msg = "weight count does not match the stencil";
+    return -1;
+  }
+  if (!march_fits<T, VX>(p)) {
+    if (msg) *msg = "launch does not fit the march kernel's layout";
+    return -1;
+  }
+  TbArgs<A> a{};
+  a.in = p.in;
+  a.out = p.out;
+  a.buf_z0 = p.buf_z0;
+  a.out_z0 = p.out_z0;
+  a.plane = p.plane;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.per_x = p.per_x;
+  a.per_y = p.per_y;
+  a.n_axis = p.n_axis;
+  a.in_lo = p.in_lo;
+  a.in_hi = p.in_hi;
+  a.out_lo = p.out_lo;
+  a.out_hi = p.out_hi;
+  for (int i = 0; i < S::npts(); ++i) a.w.w[i] = (A)p.weights[i];
+  a.ntx = (int)((p.nx + G::OX - 1) / G::OX);
+  a.nty = 1;
+  const int64_t span = p.out_hi - p.out_lo;
+  if (span <= 0) return 0;
+  // one wave per (tile, segment); aim for 4 waves per targeted workgroup
+  plan_segments(span, ((int64_t)a.ntx + 3) / 4, &a.zseg, &a.nseg);
+  const int64_t tasks = (int64_t)a.ntx * a.nseg;
+  const int64_t nwg = (tasks + 3) / 4;
+  if (nwg > 0x7fffffff / 4) {
+    if (msg) *msg = "grid too large for one launch";
+    return -1;
+  }
+  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  hipLaunchKernelGGL((march2d_kernel<T, BOX, R, KL, VX, PF, ROT>), dim3((unsigned)grid), dim3(256), 0, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (msg) *msg = std::string("kernel launch: ") + hipGetErrorString(e);
+    return -5;
+  }
+  return 0;
+}
+
 // Bytes of the march kernel's halo buffers.
 template <typename A, int KL, int NW, int R, int VX, int HB>
 constexpr size_t march_lds() {
@@ -235,6 +287,12 @@ template <typename T, int NDIM, bool BOX, int R, int KL>
 int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
   using A = typename Store<T>::A;
   constexpr size_t kLdsMax = 160 * 1024;
+  if constexpr (NDIM == 2 && SO2DR_MARCH_KERNEL) {
+    // unrolling by the stencil width is kept while the unrolled body stays
+    // within a few thousand FMAs
+    constexpr bool rot = (int64_t)KL * 4 * Stencil<2, BOX, R>::npts() * (2 * R + 1) > 2400;
+    if (march_fits<T, 4>(p)) return launch_march2d_one<T, BOX, R, KL, 4, 2, rot>(p, s, msg);
+  }
   if constexpr (NDIM == 3 && SO2DR_MARCH_KERNEL) {
     constexpr bool wide = (KL == 1 || (KL == 2 && !BOX && R == 1)) && march_lds<A, KL, 16, R, 4, 2>() <= kLdsMax;
     constexpr int HB = march_lds<A, KL, 8, R, 2, 2>() <= 65536 ? 2 : 1;

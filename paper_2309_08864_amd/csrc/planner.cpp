@@ -355,9 +355,18 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     }
     P->k_on = std::min(D.k_on, P->K);
   } else {
-    // measured best update rate per launch: 3 fused levels for the 7-point
-    // star, 2 for the 13-point star and the 27-point box, 4 for 2D rows
-    const int pref = P->ndim == 2 ? 4 : (P->r == 1 && P->shape == SO2DR_STAR ? 3 : 2);
+    // fused levels with the best measured update rate per launch on MI355X:
+    // 3D: 3 for the 7-point star, 2 for the 13-point star and the 27-point
+    // box; 2D: 8 for the 5-point star, 4 / 2 for the radius-1 / radius-2 box,
+    // 1 for wider boxes (their kernels are bound by arithmetic, and fusing
+    // only adds the tile-edge recomputation)
+    int pref = 2;
+    if (P->ndim == 3)
+      pref = P->r == 1 && P->shape == SO2DR_STAR ? 3 : 2;
+    else if (P->shape == SO2DR_STAR)
+      pref = 8;
+    else
+      pref = P->r == 1 ? 4 : (P->r == 2 ? 2 : 1);
     P->k_on = std::max(1, std::min({pref, P->max_k_on, P->K}));
   }
   P->budget = D.device_budget_bytes;

@@ -280,21 +280,24 @@ def test_bit_exact_vs_arithmetic_model(storage, ndim, shape, r):
     assert diff == 0
 
 
-@pytest.mark.parametrize("shape,r", [("star", 1), ("star", 2), ("box", 1)])
-def test_f32_row_length_fallback_kernel(shape, r):
-    """nx = 70 is not a multiple of 4 (nor of the 128-cell tile): the launcher
-    takes the register-column kernel; every fused depth against the oracle
-    and bit for bit against the in-core run."""
-    rng = np.random.default_rng(40 + r)
-    offs = _offsets(3, shape, r)
+@pytest.mark.parametrize("ndim,shape,r", [(3, "star", 1), (3, "star", 2), (3, "box", 1), (2, "star", 1),
+                                           (2, "box", 1), (2, "box", 3)])
+def test_f32_row_length_fallback_kernel(ndim, shape, r):
+    """Rows whose length is not a multiple of 4 cells (nor of the tile): the
+    launcher takes the register-column kernel in 3D and the LDS-plane kernel
+    in 2D; every fused depth up to 3 against the oracle and bit for bit
+    against the in-core run."""
+    rng = np.random.default_rng(40 + r + ndim)
+    offs = _offsets(ndim, shape, r)
     w = _weights(offs, rng)
-    nx, ny, nz = 70, 37, 29
-    u0 = rng.random((nz, ny, nx))
+    nx, ny, nz = (70, 37, 29) if ndim == 3 else (1099, 57, 1)
+    u0 = rng.random(np_shape(ndim, nx, ny, nz))
     T, K = 7, 3
-    d = max(2, min(4, nz // (2 * r * K)))
+    N = nz if ndim == 3 else ny
+    d = max(2, min(4, N // (2 * r * K)))
     us = to_storage(u0, "f32")
     ref = oracle.sweep(us.double().numpy(), offs, fp32_weights(w), T)
-    base = dict(ndim=3, nx=nx, ny=ny, nz=nz, shape=shape, radius=r, weights=list(w), T=T,
+    base = dict(ndim=ndim, nx=nx, ny=ny, nz=nz, shape=shape, radius=r, weights=list(w), T=T,
                 budget=4 << 30, storage="f32")
     incore, _, _ = gpu_run(dict(base, tb_depth=T, n_chunks=1, k_on=1), us)
     assert rel_l2(incore.double().numpy(), ref) <= 1e-5
@@ -302,4 +305,4 @@ def test_f32_row_length_fallback_kernel(shape, r):
     maxk = Plan(**dict(base, tb_depth=K, n_chunks=d)).info()["max_k_on"]
     for k_on in range(1, min(3, maxk) + 1):
         got, _, _ = gpu_run(dict(base, tb_depth=K, n_chunks=d, k_on=k_on), us)
-        assert torch.equal(got, incore), (shape, r, k_on)
+        assert torch.equal(got, incore), (ndim, shape, r, k_on)
