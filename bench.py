@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--method", default="so2dr", choices=["so2dr", "resreu"],
                     help="resreu: the paper's comparison code (per-step sharing, one-step kernels)")
+    ap.add_argument("--rounding", default="every_step", choices=["every_step", "at_store"],
+                    help="BF16/F16 storage: round after every step, or only where a launch stores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-planes", type=int, default=0)
     ap.add_argument("--compare-storage", default=None,
@@ -227,7 +229,7 @@ def main():
     plan = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
                 weights=list(w), T=wl.T, tb_depth=K, n_chunks=d, k_on=args.k_on,
                 n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic,
-                method=args.method)
+                method=args.method, rounding=args.rounding)
     info = plan.info()
     plan.bind()
     plan.set_timing(True)
@@ -286,7 +288,7 @@ def main():
             "k_on": info["k_on"], "n_slots": info["n_slots"], "budget_bytes": wl.budget,
             "workspace_bytes": info["workspace_bytes"],
             "redundant_fraction": round(info["redundant_fraction"], 4),
-            "method": args.method, "lean": info["lean"],
+            "method": args.method, "lean": info["lean"], "rounding": args.rounding,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -320,7 +322,8 @@ def main():
             h[z0:z0 + 64].copy_(master[z0:z0 + 64])
         plan2 = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
                      weights=list(w), T=wl.T, tb_depth=K, n_chunks=d, k_on=args.k_on,
-                     n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic).bind()
+                     n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic,
+                     rounding=args.rounding).bind()
         plan2.run(h)
         plan2.close()
         hm = h

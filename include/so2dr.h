@@ -63,6 +63,18 @@ typedef enum { SO2DR_DIRICHLET0 = 0, SO2DR_PERIODIC = 1 } so2dr_bc;
  * and nothing is recomputed; kept for comparison. */
 typedef enum { SO2DR_METHOD_SO2DR = 0, SO2DR_METHOD_RESREU = 1 } so2dr_method;
 
+/* When BF16/F16 storage is rounded (FP32 and FP64 storage ignore this; no
+ * counterpart in the paper, whose fields are FP32).
+ *   SO2DR_ROUND_EVERY_STEP: after every time step, also between the levels a
+ *     kernel fuses: the result depends on nothing but u0, the weights and T.
+ *   SO2DR_ROUND_AT_STORE: fused levels keep FP32 sums in registers and LDS;
+ *     only what a launch stores to HBM (every k_on steps, and at the end of
+ *     each round of tb_depth steps) is rounded.  Fewer roundings, lower
+ *     error; the result then depends on the launch schedule, and an
+ *     out-of-core run equals the in-core run of the same k_on only when
+ *     tb_depth is a multiple of k_on. */
+typedef enum { SO2DR_ROUND_EVERY_STEP = 0, SO2DR_ROUND_AT_STORE = 1 } so2dr_rounding;
+
 /* Problem and run-time configuration: the variables of the paper's Table I
  * (dim, sz, r, d, S_tot, S_TB, N_strm, C_dmem) plus the stencil itself. */
 typedef struct {
@@ -82,6 +94,7 @@ typedef struct {
   size_t device_budget_bytes; /* hard cap on the device memory the plan may use */
   int adjoint;                /* 1: also reserve what so2dr_adjoint_run needs */
   int method;                 /* so2dr_method: SO2DR_METHOD_SO2DR (default) or _RESREU */
+  int rounding;               /* an so2dr_rounding value, for 16-bit storage; 0 = every step */
 } so2dr_desc;
 
 /* What the planner chose (all sizes in bytes unless noted). */
@@ -101,6 +114,7 @@ typedef struct {
   int method;                 /* so2dr_method of the plan */
   double redundant_fraction;  /* recomputed / useful cell updates */
   int64_t n_ops;              /* entries in the operation schedule */
+  int rounding;               /* the so2dr_rounding value in effect: EVERY_STEP unless 16-bit storage */
 } so2dr_plan_info;
 
 /* One entry of the schedule the executor runs (Algorithm 1, unrolled).

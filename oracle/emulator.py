@@ -93,19 +93,21 @@ def _shifted(u, o, periodic):
     return v
 
 
-def sweep_bits(u0, offsets, weights, T, storage="f32", periodic=(0, 0, 0)):
-    """T steps of the FP32-FMA sweep with per-step rounding to `storage`
-    (f32, bf16 or f16).  u0 holds values already representable in the
-    storage type; returns float32 values.  offsets: (dz, dy, dx) in the order
-    the sums run (lexicographic); a 2D field is (y, x) with dz == 0."""
+def sweep_bits(u0, offsets, weights, T, storage="f32", periodic=(0, 0, 0), round_after=None):
+    """T steps of the FP32-FMA sweep with rounding to `storage` (f32, bf16 or
+    f16).  u0 holds values already representable in the storage type;
+    returns float32 values.  offsets: (dz, dy, dx) in the order the sums run
+    (lexicographic); a 2D field is (y, x) with dz == 0.  round_after: the
+    step counts t (1..T) after which the field is rounded to storage; None
+    rounds after every step.  Between roundings the field stays FP32."""
     two_d = np.asarray(u0).ndim == 2
     u = np.asarray(u0, np.float32)
     u = u[None] if two_d else u
     w32 = np.asarray(weights, np.float64).astype(np.float32)
     rnd = _ROUND[storage]
-    for _ in range(T):
+    for t in range(1, T + 1):
         acc = np.zeros_like(u)           # +0
         for o, wk in zip(offsets, w32):
             acc = fma32(wk, _shifted(u, o, periodic), acc)
-        u = rnd(acc)
+        u = rnd(acc) if round_after is None or t in round_after else acc
     return u[0] if two_d else u

@@ -30,6 +30,7 @@ struct LaunchParams {
   int64_t n_axis, in_lo, in_hi, out_lo, out_hi;
   const double *weights;   // npts, lexicographic
   int npts;
+  int ras = 0;             // 16-bit storage: round only what a launch stores
 };
 
 // Deepest compiled depth per storage type (so2dr_dtype) and stencil; 0 = none.

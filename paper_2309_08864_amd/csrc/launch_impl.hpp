@@ -50,7 +50,7 @@ inline void plan_segments(int64_t span, int64_t tiles, int64_t *zseg, int *nseg)
   *nseg = (int)((span + *zseg - 1) / *zseg);
 }
 
-template <typename T, int NDIM, bool BOX, int R, int KL>
+template <typename T, int NDIM, bool BOX, int R, int KL, bool RAS = false>
 int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
   using G = Tile<NDIM, R, KL>;
@@ -88,7 +88,7 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   constexpr size_t lds = tb_lds_bytes<T, NDIM, BOX, R, KL>();
   static bool attr_done = false;
   if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute((const void *)tb_kernel<T, NDIM, BOX, R, KL>,
+    hipError_t e = hipFuncSetAttribute((const void *)tb_kernel<T, NDIM, BOX, R, KL, RAS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) {
       if (msg) *msg = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
@@ -99,7 +99,7 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   // with the XCD-aware order the grid is padded to a multiple of 8 so that the
   // permutation covers every tile; padding workgroups exit at once
   const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
-  hipLaunchKernelGGL((tb_kernel<T, NDIM, BOX, R, KL>), dim3((unsigned)grid), dim3(G::NT), lds, stream, a);
+  hipLaunchKernelGGL((tb_kernel<T, NDIM, BOX, R, KL, RAS>), dim3((unsigned)grid), dim3(G::NT), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     if (msg) *msg = std::string("kernel launch: ") + hipGetErrorString(e);
@@ -109,7 +109,7 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
 }
 
 template <typename T, bool BOX, int R, int KL, int NW = SO2DR_STAR_NW, int M = SO2DR_STAR_M,
-          int VX = SO2DR_STAR_VX, int HB = SO2DR_STAR_HB>
+          int VX = SO2DR_STAR_VX, int HB = SO2DR_STAR_HB, bool RAS = false>
 int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
   using G = StarTile<R, KL, NW, M, VX>;
@@ -145,7 +145,7 @@ int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) 
     return -1;
   }
   const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
-  hipLaunchKernelGGL((col3d_kernel<T, BOX, R, KL, NW, M, VX, HB>), dim3((unsigned)grid), dim3(NW * 64), 0,
+  hipLaunchKernelGGL((col3d_kernel<T, BOX, R, KL, NW, M, VX, HB, RAS>), dim3((unsigned)grid), dim3(NW * 64), 0,
                      stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -164,7 +164,8 @@ inline bool march_fits(const LaunchParams &p) {
          p.out_z0 > -((int64_t)1 << 29) && p.in_lo < p.in_hi;
 }
 
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1>
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1,
+          bool RAS = false>
 int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
   using G = StarTile<R, KL, NW, M, VX>;
@@ -204,7 +205,7 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
     return -1;
   }
   const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
-  hipLaunchKernelGGL((march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE>), dim3((unsigned)grid), dim3(NW * 64), 0,
+  hipLaunchKernelGGL((march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE, RAS>), dim3((unsigned)grid), dim3(NW * 64), 0,
                      stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -214,7 +215,7 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
   return 0;
 }
 
-template <typename T, bool BOX, int R, int KL, int VX, int PF, bool ROT>
+template <typename T, bool BOX, int R, int KL, int VX, int PF, bool ROT, bool RAS = false>
 int launch_march2d_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
   using G = RowTile<R, KL, VX>;
@@ -256,7 +257,7 @@ int launch_march2d_one(const LaunchParams &p, hipStream_t stream, std::string *m
     return -1;
   }
   const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
-  hipLaunchKernelGGL((march2d_kernel<T, BOX, R, KL, VX, PF, ROT>), dim3((unsigned)grid), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL((march2d_kernel<T, BOX, R, KL, VX, PF, ROT, RAS>), dim3((unsigned)grid), dim3(256), 0, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     if (msg) *msg = std::string("kernel launch: ") + hipGetErrorString(e);
@@ -283,7 +284,7 @@ constexpr size_t march_lds() {
 //   * grids whose row length is not a multiple of the cells per lane fall
 //     back to the register-column kernel, 2D grids and whatever does not fit
 //     to the LDS-plane kernel.
-template <typename T, int NDIM, bool BOX, int R, int KL>
+template <typename T, int NDIM, bool BOX, int R, int KL, bool RAS>
 int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
   using A = typename Store<T>::A;
   constexpr size_t kLdsMax = 160 * 1024;
@@ -291,44 +292,54 @@ int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
     // unrolling by the stencil width is kept while the unrolled body stays
     // within a few thousand FMAs
     constexpr bool rot = (int64_t)KL * 4 * Stencil<2, BOX, R>::npts() * (2 * R + 1) > 2400;
-    if (march_fits<T, 4>(p)) return launch_march2d_one<T, BOX, R, KL, 4, 2, rot>(p, s, msg);
+    if (march_fits<T, 4>(p)) return launch_march2d_one<T, BOX, R, KL, 4, 2, rot, RAS>(p, s, msg);
   }
   if constexpr (NDIM == 3 && SO2DR_MARCH_KERNEL) {
     constexpr bool wide = (KL == 1 || (KL == 2 && !BOX && R == 1)) && march_lds<A, KL, 16, R, 4, 2>() <= kLdsMax;
     constexpr int HB = march_lds<A, KL, 8, R, 2, 2>() <= 65536 ? 2 : 1;
     if constexpr (wide) {
-      if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 16, 2, 4, 2, 2>(p, s, msg);
+      if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 16, 2, 4, 2, 2, 1, RAS>(p, s, msg);
     } else if constexpr (march_lds<A, KL, 8, R, 2, HB>() <= kLdsMax && 2 * ((KL * R + 1) / 2) < 32 &&
                          4 >= R && 32 > 2 * KL * R) {
-      if (march_fits<T, 2>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 2, HB, 2>(p, s, msg);
+      if (march_fits<T, 2>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 2, HB, 2, 1, RAS>(p, s, msg);
     }
   }
   constexpr size_t lds1 = sizeof(A) * KL * 1 * 16 * 2 * R * 64 * 4;
   constexpr size_t ldsn = sizeof(A) * KL * 2 * 4 * 2 * R * 64 * 1;
   if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL == 1 && lds1 <= 65536)
-    return launch_col_one<T, BOX, R, KL, 16, 2, 4, 1>(p, s, msg);
+    return launch_col_one<T, BOX, R, KL, 16, 2, 4, 1, RAS>(p, s, msg);
   else if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL >= 2 && 2 * KL * R < 32 && ldsn <= 65536)
-    return launch_col_one<T, BOX, R, KL, 4, 8, 1, 2>(p, s, msg);
+    return launch_col_one<T, BOX, R, KL, 4, 8, 1, 2, RAS>(p, s, msg);
   else
-    return launch_one<T, NDIM, BOX, R, KL>(p, s, msg);
+    return launch_one<T, NDIM, BOX, R, KL, RAS>(p, s, msg);
 }
 
 // Expand one stencil's depths 1..MAXKL into a switch on p.kl.
-template <typename T, int NDIM, bool BOX, int R, int MAXKL>
-int launch_depth(const LaunchParams &p, hipStream_t s, std::string *msg) {
+template <typename T, int NDIM, bool BOX, int R, int MAXKL, bool RAS>
+int launch_depth_r(const LaunchParams &p, hipStream_t s, std::string *msg) {
   switch (p.kl) {
-    case 1: return launch_any<T, NDIM, BOX, R, 1>(p, s, msg);
-    case 2: if constexpr (MAXKL >= 2) return launch_any<T, NDIM, BOX, R, 2>(p, s, msg); else break;
-    case 3: if constexpr (MAXKL >= 3) return launch_any<T, NDIM, BOX, R, 3>(p, s, msg); else break;
-    case 4: if constexpr (MAXKL >= 4) return launch_any<T, NDIM, BOX, R, 4>(p, s, msg); else break;
-    case 5: if constexpr (MAXKL >= 5) return launch_any<T, NDIM, BOX, R, 5>(p, s, msg); else break;
-    case 6: if constexpr (MAXKL >= 6) return launch_any<T, NDIM, BOX, R, 6>(p, s, msg); else break;
-    case 7: if constexpr (MAXKL >= 7) return launch_any<T, NDIM, BOX, R, 7>(p, s, msg); else break;
-    case 8: if constexpr (MAXKL >= 8) return launch_any<T, NDIM, BOX, R, 8>(p, s, msg); else break;
+    case 1: return launch_any<T, NDIM, BOX, R, 1, RAS>(p, s, msg);
+    case 2: if constexpr (MAXKL >= 2) return launch_any<T, NDIM, BOX, R, 2, RAS>(p, s, msg); else break;
+    case 3: if constexpr (MAXKL >= 3) return launch_any<T, NDIM, BOX, R, 3, RAS>(p, s, msg); else break;
+    case 4: if constexpr (MAXKL >= 4) return launch_any<T, NDIM, BOX, R, 4, RAS>(p, s, msg); else break;
+    case 5: if constexpr (MAXKL >= 5) return launch_any<T, NDIM, BOX, R, 5, RAS>(p, s, msg); else break;
+    case 6: if constexpr (MAXKL >= 6) return launch_any<T, NDIM, BOX, R, 6, RAS>(p, s, msg); else break;
+    case 7: if constexpr (MAXKL >= 7) return launch_any<T, NDIM, BOX, R, 7, RAS>(p, s, msg); else break;
+    case 8: if constexpr (MAXKL >= 8) return launch_any<T, NDIM, BOX, R, 8, RAS>(p, s, msg); else break;
     default: break;
   }
   if (msg) *msg = "fused depth not built for this stencil";
   return -3;
+}
+
+// Round-at-store variants exist for the 16-bit storage types only: FP32 and
+// FP64 storage rounds nothing between levels either way.
+template <typename T, int NDIM, bool BOX, int R, int MAXKL>
+int launch_depth(const LaunchParams &p, hipStream_t s, std::string *msg) {
+  if constexpr (sizeof(T) == 2) {
+    if (p.ras) return launch_depth_r<T, NDIM, BOX, R, MAXKL, true>(p, s, msg);
+  }
+  return launch_depth_r<T, NDIM, BOX, R, MAXKL, false>(p, s, msg);
 }
 
 }  // namespace so2dr

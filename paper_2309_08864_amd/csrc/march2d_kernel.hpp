@@ -39,7 +39,7 @@ struct RowTile {
   static_assert(R <= 2 * VX && OX > 0, "tile too small for this depth");
 };
 
-template <typename T, bool BOX, int R, int KL, int VX, int PF, bool ROT, bool GH>
+template <typename T, bool BOX, int R, int KL, int VX, int PF, bool ROT, bool RAS, bool GH>
 __device__ __forceinline__ void march2d_tile(const TbArgs<typename Store<T>::A> &a, int lane, int tx_i,
                                              int zo0, int zo1) {
   using A = typename Store<T>::A;
@@ -129,7 +129,8 @@ __device__ __forceinline__ void march2d_tile(const TbArgs<typename Store<T>::A> 
               }
               acc[l - 1][j][slot] = sum;
             }
-            res[j] = Store<T>::round(acc[l - 1][j][ROT ? 2 * R : pmod(EP - R, W)]);
+            const A v = acc[l - 1][j][ROT ? 2 * R : pmod(EP - R, W)];
+            res[j] = RAS && l < KL ? v : Store<T>::round(v);
             if constexpr (ROT) {  // output e - R is done: every sum moves one slot up
 #pragma unroll
               for (int k = 2 * R; k > 0; --k) acc[l - 1][j][k] = acc[l - 1][j][k - 1];
@@ -154,8 +155,10 @@ __device__ __forceinline__ void march2d_tile(const TbArgs<typename Store<T>::A> 
     unroll_seq([&](auto ph) { step(ph, s + decltype(ph)::value); }, std::make_integer_sequence<int, U>{});
 }
 
-// 4 independent waves per workgroup; wave task = (tile, segment).
-template <typename T, bool BOX, int R, int KL, int VX, int PF, bool ROT>
+// 4 independent waves per workgroup; wave task = (tile, segment).  RAS (round
+// at store): levels below the last keep FP32 sums; only the value a launch
+// stores is rounded to the storage type.
+template <typename T, bool BOX, int R, int KL, int VX, int PF, bool ROT, bool RAS = false>
 __global__ __launch_bounds__(256) void march2d_kernel(const TbArgs<typename Store<T>::A> a) {
   using G = RowTile<R, KL, VX>;
   const int lane = threadIdx.x & 63;
@@ -182,9 +185,9 @@ __global__ __launch_bounds__(256) void march2d_kernel(const TbArgs<typename Stor
   const bool ghosts = (!a.per_x && (x_lo < 0 || x_lo + G::TX > a.nx)) || P0 - 2 * R < 0 ||
                       P0 + n_load + R > (int)a.n_axis;
   if (ghosts)
-    march2d_tile<T, BOX, R, KL, VX, PF, ROT, true>(a, lane, tx_i, zo0, zo1);
+    march2d_tile<T, BOX, R, KL, VX, PF, ROT, RAS, true>(a, lane, tx_i, zo0, zo1);
   else
-    march2d_tile<T, BOX, R, KL, VX, PF, ROT, false>(a, lane, tx_i, zo0, zo1);
+    march2d_tile<T, BOX, R, KL, VX, PF, ROT, RAS, false>(a, lane, tx_i, zo0, zo1);
 }
 
 }  // namespace so2dr

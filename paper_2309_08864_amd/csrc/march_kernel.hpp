@@ -46,14 +46,15 @@ __device__ __forceinline__ void unroll_seq(F &&f, std::integer_sequence<int, I..
 
 constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool GH>
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool RAS, bool GH>
 __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> &a,
                                              typename Store<T>::A (*halo)[HB][NW][2 * R][64 * VX],
                                              int lane, int wave, int tx_i, int ty_i, int zo0, int zo1);
 
 // WPE: waves per SIMD the register allocation must allow (caps VGPRs at
-// 512 / WPE)
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1>
+// 512 / WPE).  RAS (round at store): levels below the last keep FP32 sums;
+// only the value a launch stores is rounded to the storage type.
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1, bool RAS = false>
 __global__ __launch_bounds__(NW * 64, WPE) void march3d_kernel(const TbArgs<typename Store<T>::A> a) {
   using A = typename Store<T>::A;
   using G = StarTile<R, KL, NW, M, VX>;
@@ -88,12 +89,12 @@ __global__ __launch_bounds__(NW * 64, WPE) void march3d_kernel(const TbArgs<type
                       (!a.per_y && (y_lo < 0 || y_lo + G::TY > a.ny)) || P0 - 2 * R < 0 ||
                       P0 + n_load + R > (int)a.n_axis;
   if (ghosts)
-    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, true>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
+    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, RAS, true>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
   else
-    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, false>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
+    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, RAS, false>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
 }
 
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool GH>
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool RAS, bool GH>
 __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> &a,
                                              typename Store<T>::A (*halo)[HB][NW][2 * R][64 * VX],
                                              int lane, int wave, int tx_i, int ty_i, int zo0, int zo1) {
@@ -242,7 +243,8 @@ __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> 
                   }
                 acc[l - 1][m][j][slot] = sum;
               }
-              res[m][j] = Store<T>::round(acc[l - 1][m][j][pmod(EP - R, W)]);
+              const A v = acc[l - 1][m][j][pmod(EP - R, W)];
+              res[m][j] = RAS && l < KL ? v : Store<T>::round(v);
             }
           if constexpr (GH) {
             const bool zg = q < 0 || q >= n_axis;

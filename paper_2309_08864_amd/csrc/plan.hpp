@@ -30,6 +30,7 @@ struct Plan {
   bool adjoint = false;
   int bufs_per_slot = 2;           // 2 ping-pong buffers; 5 when the adjoint is planned
   bool resreu = false;             // comparison method: per-step sharing, single-step kernels
+  int ras = 0;                     // 16-bit storage rounded only where a launch stores
   bool lean = false;               // 1 buffer per slot, kernels split into shifted sub-blocks
   int lean_block = 0;              // output planes per sub-block launch
   int64_t lean_extra = 0;          // spare planes below the round-start data

@@ -376,6 +376,11 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     return SO2DR_E_INVALID;
   }
   P->resreu = D.method == SO2DR_METHOD_RESREU;
+  if (D.rounding != SO2DR_ROUND_EVERY_STEP && D.rounding != SO2DR_ROUND_AT_STORE) {
+    set_error("unknown rounding mode");
+    return SO2DR_E_INVALID;
+  }
+  P->ras = D.rounding == SO2DR_ROUND_AT_STORE && (P->dtype == SO2DR_BF16 || P->dtype == SO2DR_F16);
   if (P->resreu) {
     if (P->adjoint) {
       set_error("the comparison method has no adjoint");

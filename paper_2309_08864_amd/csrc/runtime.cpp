@@ -245,6 +245,7 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
         lp.out_hi = op.z1;
         lp.weights = P.weights.data();
         lp.npts = (int)P.weights.size();
+        lp.ras = P.ras;
         rc = launch_tb(P.dtype, lp, s, &msg);
         if (rc) {
           set_error(msg);

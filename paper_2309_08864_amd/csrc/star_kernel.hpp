@@ -125,7 +125,7 @@ struct StarTile {
   static_assert(M >= R && R <= 2 * VX && OX > 0 && OY > 0, "tile too small for this depth");
 };
 
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX_, int HB>
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX_, int HB, bool RAS = false>
 __global__ __launch_bounds__(NW * 64) void col3d_kernel(const TbArgs<typename Store<T>::A> a) {
   using A = typename Store<T>::A;
   using S = Stencil<3, BOX, R>;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(NW * 64) void col3d_kernel(const TbArgs<typename St
               }
             acc[l - 1][m][j][R + dz] = s;
           }
-          A res = Store<T>::round(acc[l - 1][m][j][2 * R]);
+          A res = RAS && l < KL ? acc[l - 1][m][j][2 * R] : Store<T>::round(acc[l - 1][m][j][2 * R]);
           if (zghost || ghy[m] || ghx[j]) res = A(0);
 #pragma unroll
           for (int k = 2 * R; k > 0; --k) acc[l - 1][m][j][k] = acc[l - 1][m][j][k - 1];

@@ -166,7 +166,9 @@ struct Tile {
   static_assert(OX > 0 && OY > 0, "tile too small for this depth");
 };
 
-template <typename T, int NDIM, bool BOX, int R, int KL>
+// RAS (round at store): levels below the last keep FP32 sums; only the value
+// a launch stores is rounded to the storage type.
+template <typename T, int NDIM, bool BOX, int R, int KL, bool RAS = false>
 __global__ __launch_bounds__(256) void tb_kernel(const TbArgs<typename Store<T>::A> a) {
   using A = typename Store<T>::A;
   using S = Stencil<NDIM, BOX, R>;
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(256) void tb_kernel(const TbArgs<typename Store<T>:
             }
           acc[l - 1][c][R + dz] = s;
         }
-        A res = Store<T>::round(acc[l - 1][c][2 * R]);
+        A res = RAS && l < KL ? acc[l - 1][c][2 * R] : Store<T>::round(acc[l - 1][c][2 * R]);
         if (zghost || ghost[c]) res = A(0);
         // rotate: output p + R - k moves to slot k + 1
 #pragma unroll

@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import DTYPES, METHODS, OP_KINDS, SHAPES, check, lib
+from ._lib import DTYPES, METHODS, OP_KINDS, ROUNDING, SHAPES, check, lib
 
 TORCH_DTYPES = {"f32": "float32", "f64": "float64", "bf16": "bfloat16", "f16": "float16"}
 
@@ -33,11 +33,13 @@ class Plan:
 
     Grid extents are (nx, ny, nz) with x contiguous; a 2D grid has nz == 1
     and is cut along y.  ``weights`` follows stencil_offsets' order.
-    ``bc`` gives, per axis x, y, z, 0 for zero Dirichlet or 1 for periodic."""
+    ``bc`` gives, per axis x, y, z, 0 for zero Dirichlet or 1 for periodic.
+    ``rounding`` ("every_step" or "at_store") applies to BF16/F16 storage:
+    round after every step, or only where a launch stores to HBM."""
 
     def __init__(self, *, ndim, nx, ny, nz=1, shape="star", radius=1, weights, T, tb_depth=0,
                  n_chunks=0, k_on=0, n_slots=0, budget, storage="f32", bc=(0, 0, 0),
-                 adjoint=False, method="so2dr"):
+                 adjoint=False, method="so2dr", rounding="every_step"):
         self.storage = storage
         self.shape3 = (nz, ny, nx)
         self._T = T
@@ -54,6 +56,7 @@ class Plan:
         d.device_budget_bytes = int(budget)
         d.adjoint = 1 if adjoint else 0
         d.method = METHODS[method]
+        d.rounding = ROUNDING[rounding]
         h = ctypes.c_void_p()
         check(lib().so2dr_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h

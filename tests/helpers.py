@@ -62,3 +62,20 @@ def rel_l2(a, b):
 
 def fp32_weights(w):
     return np.asarray(w, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def store_steps(T, K, k_on):
+    """Step counts after which a plan stores the field to HBM: rounds of K
+    steps (the last one shorter), and inside a round one store per launch of
+    k_on steps plus one for the remainder -- the documented schedule of
+    round-at-store BF16/F16 plans."""
+    out = set()
+    t0 = 0
+    while t0 < T:
+        kp = min(K, T - t0)
+        t = t0
+        while t < t0 + kp:
+            t = min(t + k_on, t0 + kp)
+            out.add(t)
+        t0 += kp
+    return out

@@ -85,3 +85,34 @@ def test_sweep_bits_vs_oracle(ndim, shape, r):
     ub = em.round_bf16(u0)
     gb = em.sweep_bits(ub, offs, w32, T, "bf16")
     assert np.array_equal(gb, em.round_bf16(gb))
+
+
+def test_round_after_schedule_semantics():
+    """round_after: no rounding equals the FP32 sweep; rounding only after the
+    last step equals the rounded FP32 sweep; a schedule {2, T} equals two
+    FP32 sweeps with a rounding after each; every step equals the default."""
+    rng = np.random.default_rng(9)
+    offs = oracle.stencil_offsets(3, "star", 1)
+    w = rng.uniform(0.1, 1, len(offs))
+    w32 = (w / w.sum()).astype(np.float32).astype(np.float64)
+    u0 = em.round_bf16(rng.random((6, 7, 8)).astype(np.float32))
+    T = 4
+    f32 = em.sweep_bits(u0, offs, w32, T, "f32")
+    assert np.array_equal(em.sweep_bits(u0, offs, w32, T, "bf16", round_after=set()), f32)
+    assert np.array_equal(em.sweep_bits(u0, offs, w32, T, "bf16", round_after={T}), em.round_bf16(f32))
+    half = em.round_bf16(em.sweep_bits(u0, offs, w32, 2, "f32"))
+    two = em.round_bf16(em.sweep_bits(half, offs, w32, 2, "f32"))
+    assert np.array_equal(em.sweep_bits(u0, offs, w32, T, "bf16", round_after={2, T}), two)
+    assert np.array_equal(em.sweep_bits(u0, offs, w32, T, "bf16", round_after=set(range(1, T + 1))),
+                          em.sweep_bits(u0, offs, w32, T, "bf16"))
+
+
+def test_store_steps_schedule():
+    """The documented store schedule: one store per launch of k_on steps inside
+    each round of K steps, one for a round's remainder (hand-worked cases)."""
+    from helpers import store_steps
+    assert store_steps(10, 4, 2) == {2, 4, 6, 8, 10}
+    assert store_steps(10, 4, 3) == {3, 4, 7, 8, 10}
+    assert store_steps(7, 3, 3) == {3, 6, 7}
+    assert store_steps(5, 8, 2) == {2, 4, 5}
+    assert store_steps(6, 6, 1) == {1, 2, 3, 4, 5, 6}
