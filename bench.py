@@ -68,6 +68,11 @@ def parse():
                     help="resreu: the paper's comparison code (per-step sharing, one-step kernels)")
     ap.add_argument("--rounding", default="every_step", choices=["every_step", "at_store"],
                     help="BF16/F16 storage: round after every step, or only where a launch stores")
+    ap.add_argument("--auto", action="store_true",
+                    help="let the cost model choose chunks, k_on and slots (the TB depth stays "
+                         "the workload's unless --auto-depth)")
+    ap.add_argument("--auto-depth", action="store_true", help="with --auto: choose the TB depth too")
+    ap.add_argument("--T", type=int, default=0, help="override the workload's number of time steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-planes", type=int, default=0)
     ap.add_argument("--compare-storage", default=None,
@@ -217,6 +222,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     wl = workloads.CONFIGS[args.workload]
+    if args.T:
+        import dataclasses
+        wl = dataclasses.replace(wl, T=args.T)
     storage = args.storage or wl.dtypes[0]
     offs = stencil_offsets(wl.ndim, wl.shape, wl.radius)
     w = weights_for(wl, offs)
@@ -226,11 +234,20 @@ def main():
         return bench_adjoint(args, wl, w)
     K = args.tb_depth or wl.tb_depth
     d = args.chunks or wl.n_chunks
+    if args.auto:
+        from paper_2309_08864_amd import suggest
+        kw, _ = suggest(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape,
+                        radius=wl.radius, weights=list(w), T=wl.T,
+                        tb_depth=0 if args.auto_depth else K, n_chunks=args.chunks,
+                        k_on=args.k_on, n_slots=args.slots, budget=wl.budget, storage=storage,
+                        bc=wl.periodic, method=args.method, rounding=args.rounding)
+        K, d, args.k_on, args.slots = kw["tb_depth"], kw["n_chunks"], kw["k_on"], kw["n_slots"]
     plan = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
                 weights=list(w), T=wl.T, tb_depth=K, n_chunks=d, k_on=args.k_on,
                 n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic,
                 method=args.method, rounding=args.rounding)
     info = plan.info()
+    predicted_ms = plan.predict()
     plan.bind()
     plan.set_timing(True)
     tdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16,
@@ -289,6 +306,7 @@ def main():
             "workspace_bytes": info["workspace_bytes"],
             "redundant_fraction": round(info["redundant_fraction"], 4),
             "method": args.method, "lean": info["lean"], "rounding": args.rounding,
+            "planned_by": "cost model" if args.auto else "given",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -308,6 +326,7 @@ def main():
             if tot["d2h_ms"] else None,
             "link_bound_GCells": round(LINK_PEAK_GBPS * 1e9 / (2 * h.element_size()) * info["tb_depth"] / 1e9, 1),
         },
+        "model": {"predicted_ms_per_step": round(predicted_ms, 2)},
         "cpu_baseline": None,
     }
     plan.close()

@@ -219,6 +219,41 @@ int so2dr_adjoint_run(struct so2dr_plan *plan, const void *host_u0, const void *
                       void *host_grad_u0, double *grad_w, double *loss, int ckpt_every,
                       void *const *host_ckpt, int n_ckpt, so2dr_stats *st);
 
+/* Machine figures for the cost model (no counterpart in the paper, which
+ * leaves the automatic choice of chunk count and TB depth to future work,
+ * Sec. IV-C and VII).  Rates in GB/s (1e9 bytes) and G cell-updates/s. */
+typedef struct {
+  double h2d_gbps, d2h_gbps;   /* pinned host copies, each direction alone */
+  double duplex_gbps;          /* both directions at once, together */
+  double d2d_gbps;             /* device-to-device copies */
+  double launch_us;            /* fixed cost of one kernel launch */
+  double gupd[8];              /* output cells x levels per second of a fused
+                                  launch of 1..8 levels; 0 = not available */
+} so2dr_machine;
+
+/* Fill *m with the library's built-in figures for this plan's stencil and
+ * storage type (measured on MI355X: link rates of pinned copies, per-depth
+ * update rates of the fused kernels).  Returns SO2DR_OK or E_INVALID. */
+int so2dr_machine_default(const struct so2dr_plan *plan, so2dr_machine *m);
+
+/* Predicted wall time in ms of `steps` steps (0 = the plan's T) of this plan:
+ * its own operation schedule replayed through the executor's stream and
+ * event rules with durations from *m (NULL = the built-in figures). */
+int so2dr_plan_predict(const struct so2dr_plan *plan, const so2dr_machine *m, int steps,
+                       double *ms);
+
+/* Search the fields the caller left 0 -- tb_depth (K), n_chunks (d), k_on,
+ * n_slots -- for the plan with the least predicted time that fits
+ * device_budget_bytes, and write the completed descriptor to *out (the
+ * weights pointer is copied, not the weights).  K is taken from a geometric
+ * set up to T, d up to 32 and to the 2rK-planes-per-chunk limit; a
+ * candidate replaces a cheaper-looking earlier one (fewer chunks, levels or
+ * shallower rounds) only when predicted more than 1 % faster.  *ms (may be
+ * NULL) receives the predicted time.  Returns SO2DR_OK, the descriptor's
+ * validation error, or E_BUDGET when no candidate fits. */
+int so2dr_plan_suggest(const so2dr_desc *desc, const so2dr_machine *m, so2dr_desc *out,
+                       double *ms);
+
 /* Message describing the last error on this thread ("" if none). */
 const char *so2dr_last_error(void);
 

@@ -21,7 +21,8 @@ OP_KINDS = {0: "H2D", 1: "RS_READ", 2: "RS_WRITE", 3: "KERNEL", 4: "D2H"}
 EXPORTS = ["so2dr_plan_create", "so2dr_plan_destroy", "so2dr_plan_get_info",
            "so2dr_plan_workspace_bytes", "so2dr_plan_get_ops", "so2dr_plan_bind",
            "so2dr_plan_set_timing", "so2dr_run", "so2dr_run_steps", "so2dr_adjoint_run",
-           "so2dr_last_error", "so2dr_version"]
+           "so2dr_last_error", "so2dr_version", "so2dr_machine_default", "so2dr_plan_predict",
+           "so2dr_plan_suggest"]
 
 
 class Desc(ctypes.Structure):
@@ -32,6 +33,12 @@ class Desc(ctypes.Structure):
                 ("n_chunks", ctypes.c_int), ("tb_depth", ctypes.c_int), ("k_on", ctypes.c_int),
                 ("n_slots", ctypes.c_int), ("device_budget_bytes", ctypes.c_size_t),
                 ("adjoint", ctypes.c_int), ("method", ctypes.c_int), ("rounding", ctypes.c_int)]
+
+
+class Machine(ctypes.Structure):
+    _fields_ = [("h2d_gbps", ctypes.c_double), ("d2h_gbps", ctypes.c_double),
+                ("duplex_gbps", ctypes.c_double), ("d2d_gbps", ctypes.c_double),
+                ("launch_us", ctypes.c_double), ("gupd", ctypes.c_double * 8)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -93,11 +100,17 @@ def lib():
         L.so2dr_adjoint_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(vp),
                                         i32, ctypes.POINTER(Stats)]
+        L.so2dr_machine_default.argtypes = [vp, ctypes.POINTER(Machine)]
+        L.so2dr_plan_predict.argtypes = [vp, ctypes.POINTER(Machine), i32,
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.so2dr_plan_suggest.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(Machine),
+                                         ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_double)]
         L.so2dr_last_error.restype = ctypes.c_char_p
         L.so2dr_version.restype = ctypes.c_char_p
         for f in ("so2dr_plan_create", "so2dr_plan_get_info", "so2dr_plan_workspace_bytes",
                   "so2dr_plan_get_ops", "so2dr_plan_bind", "so2dr_plan_set_timing", "so2dr_run",
-                  "so2dr_run_steps", "so2dr_adjoint_run"):
+                  "so2dr_run_steps", "so2dr_adjoint_run", "so2dr_machine_default",
+                  "so2dr_plan_predict", "so2dr_plan_suggest"):
             getattr(L, f).restype = i32
         _LIB = L
     return _LIB

@@ -21,12 +21,24 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract
           "-I", os.path.join(os.path.dirname(HERE), "include"), "-Wall", "-Wno-unused-function"]
 
 SOURCES = ["kernels_f32.hip", "kernels_f64.hip", "kernels_bf16.hip", "kernels_f16.hip",
-           "aux_kernels.hip", "planner.cpp", "runtime.cpp", "adjoint.cpp", "capi.cpp"]
+           "aux_kernels.hip", "planner.cpp", "runtime.cpp", "adjoint.cpp", "model.cpp", "capi.cpp"]
 
 
-def _compile(src: str) -> str:
+def _deps_mtime(src: str) -> float:
+    """Latest modification time of a source and of every header it can use
+    (all headers of csrc/ and include/)."""
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    files = [os.path.join(CSRC, src)]
+    files += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    files += [os.path.join(inc, f) for f in os.listdir(inc)]
+    return max(os.path.getmtime(f) for f in files)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJ, src + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _deps_mtime(src):
+        return obj
     cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
@@ -36,11 +48,14 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:
+    """Compile every source and link libso2dr.so.  incremental=True keeps an
+    object newer than its source and every header (a development shortcut;
+    the default always recompiles)."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=min(jobs, 16)) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -18,6 +18,9 @@ int bind_plan(Plan &P, void *arena, size_t bytes, void *const *streams, int n_st
 int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats *st);
 int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, double *grad_w,
                 double *loss, int ckpt_every, void *const *ckpt, int n_ckpt, so2dr_stats *st);
+void default_machine(const Plan &P, so2dr_machine *m);
+double predict_seconds(const Plan &P, const so2dr_machine &m, int steps);
+int suggest(const so2dr_desc &in, const so2dr_machine *mp, so2dr_desc *out, double *pred_ms);
 }  // namespace so2dr
 
 using so2dr::set_error;
@@ -127,6 +130,40 @@ int so2dr_plan_get_ops(const so2dr_plan *plan, so2dr_op *ops, int64_t n) {
   }
   if (n > 0) std::memcpy(ops, all.data(), sizeof(so2dr_op) * (size_t)n);
   return SO2DR_OK;
+  GUARD_END
+}
+
+int so2dr_machine_default(const so2dr_plan *plan, so2dr_machine *m) {
+  GUARD_BEGIN
+  if (!plan || !m) {
+    set_error("null plan or machine");
+    return SO2DR_E_INVALID;
+  }
+  so2dr::default_machine(plan->p, m);
+  return SO2DR_OK;
+  GUARD_END
+}
+
+int so2dr_plan_predict(const so2dr_plan *plan, const so2dr_machine *m, int steps, double *ms) {
+  GUARD_BEGIN
+  if (!plan || !ms || steps < 0) {
+    set_error("null plan or output, or negative steps");
+    return SO2DR_E_INVALID;
+  }
+  so2dr_machine dm;
+  if (!m) so2dr::default_machine(plan->p, &dm);
+  *ms = 1e3 * so2dr::predict_seconds(plan->p, m ? *m : dm, steps ? steps : plan->p.T);
+  return SO2DR_OK;
+  GUARD_END
+}
+
+int so2dr_plan_suggest(const so2dr_desc *desc, const so2dr_machine *m, so2dr_desc *out, double *ms) {
+  GUARD_BEGIN
+  if (!desc || !out) {
+    set_error("null descriptor or output");
+    return SO2DR_E_INVALID;
+  }
+  return so2dr::suggest(*desc, m, out, ms);
   GUARD_END
 }
 

@@ -44,19 +44,10 @@ class Plan:
         self.shape3 = (nz, ny, nx)
         self._T = T
         self._nw = len(weights)
-        self._w = (ctypes.c_double * len(weights))(*[float(x) for x in weights])
-        d = _lib.Desc()
-        d.ndim, d.nx, d.ny, d.nz = ndim, nx, ny, nz
-        d.shape, d.radius = SHAPES[shape], radius
-        d.weights = ctypes.cast(self._w, ctypes.POINTER(ctypes.c_double))
-        d.n_weights = len(weights)
-        d.bc = (ctypes.c_int * 3)(*bc)
-        d.storage = DTYPES[storage]
-        d.T, d.n_chunks, d.tb_depth, d.k_on, d.n_slots = T, n_chunks, tb_depth, k_on, n_slots
-        d.device_budget_bytes = int(budget)
-        d.adjoint = 1 if adjoint else 0
-        d.method = METHODS[method]
-        d.rounding = ROUNDING[rounding]
+        d, self._w = _make_desc(ndim=ndim, nx=nx, ny=ny, nz=nz, shape=shape, radius=radius,
+                                weights=weights, T=T, tb_depth=tb_depth, n_chunks=n_chunks,
+                                k_on=k_on, n_slots=n_slots, budget=budget, storage=storage,
+                                bc=bc, adjoint=adjoint, method=method, rounding=rounding)
         h = ctypes.c_void_p()
         check(lib().so2dr_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -80,6 +71,20 @@ class Plan:
             d["kind"] = OP_KINDS[d["kind"]]
             out.append(d)
         return out
+
+    def machine(self):
+        """The built-in machine figures for this plan's stencil and storage."""
+        m = _lib.Machine()
+        check(lib().so2dr_machine_default(self._h, ctypes.byref(m)))
+        return _machine_dict(m)
+
+    def predict(self, steps=0, machine=None):
+        """Predicted wall time (ms) of `steps` steps (0 = T) from the cost
+        model; `machine` is a dict like machine()'s (None = built-in)."""
+        ms = ctypes.c_double()
+        mp = ctypes.byref(_machine_struct(machine)) if machine else None
+        check(lib().so2dr_plan_predict(self._h, mp, int(steps), ctypes.byref(ms)))
+        return ms.value
 
     # ------------------------------------------------------------ device
     def bind(self, device="cuda", n_streams=None):
@@ -131,6 +136,58 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _make_desc(*, ndim, nx, ny, nz, shape, radius, weights, T, tb_depth, n_chunks, k_on, n_slots,
+               budget, storage, bc, adjoint, method, rounding):
+    w = (ctypes.c_double * len(weights))(*[float(x) for x in weights])
+    d = _lib.Desc()
+    d.ndim, d.nx, d.ny, d.nz = ndim, nx, ny, nz
+    d.shape, d.radius = SHAPES[shape], radius
+    d.weights = ctypes.cast(w, ctypes.POINTER(ctypes.c_double))
+    d.n_weights = len(weights)
+    d.bc = (ctypes.c_int * 3)(*bc)
+    d.storage = DTYPES[storage]
+    d.T, d.n_chunks, d.tb_depth, d.k_on, d.n_slots = T, n_chunks, tb_depth, k_on, n_slots
+    d.device_budget_bytes = int(budget)
+    d.adjoint = 1 if adjoint else 0
+    d.method = METHODS[method]
+    d.rounding = ROUNDING[rounding]
+    return d, w
+
+
+def _machine_dict(m):
+    out = {k: getattr(m, k) for k, _ in m._fields_ if k != "gupd"}
+    out["gupd"] = list(m.gupd)
+    return out
+
+
+def _machine_struct(md):
+    m = _lib.Machine()
+    for k, v in md.items():
+        if k == "gupd":
+            m.gupd = (ctypes.c_double * 8)(*(list(v) + [0.0] * (8 - len(v))))
+        else:
+            setattr(m, k, float(v))
+    return m
+
+
+def suggest(machine=None, **plan_kwargs):
+    """Fill the plan parameters left 0 or unset (tb_depth, n_chunks, k_on,
+    n_slots) with the combination of least predicted time that fits the
+    budget.  Returns (plan keyword arguments, predicted ms)."""
+    kw = dict(nz=1, shape="star", radius=1, tb_depth=0, n_chunks=0, k_on=0, n_slots=0,
+              storage="f32", bc=(0, 0, 0), adjoint=False, method="so2dr", rounding="every_step")
+    kw.update(plan_kwargs)
+    d, keep = _make_desc(**kw)
+    out = _lib.Desc()
+    ms = ctypes.c_double()
+    mp = ctypes.byref(_machine_struct(machine)) if machine else None
+    check(lib().so2dr_plan_suggest(ctypes.byref(d), mp, ctypes.byref(out), ctypes.byref(ms)))
+    del keep
+    res = dict(kw, tb_depth=out.tb_depth, n_chunks=out.n_chunks, k_on=out.k_on,
+               n_slots=out.n_slots)
+    return res, ms.value
 
 
 def adjoint_buffers_needed(T, tb_depth, ckpt_every):
