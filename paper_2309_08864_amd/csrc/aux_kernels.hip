@@ -27,6 +27,31 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return r;
 }
 
+// Device-to-device copy on the caller's stream, by a kernel of our own (the
+// region-sharing copies): 16-byte accesses where both ends allow, else 4 or 1.
+template <typename W>
+__global__ __launch_bounds__(256) void dcopy_kernel(W *__restrict__ dst, const W *__restrict__ src, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+int launch_dcopy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return 0;
+  const uintptr_t a = (uintptr_t)dst | (uintptr_t)src;
+  const int grid = 1024;
+  if (a % 16 == 0 && bytes % 16 == 0) {
+    hipLaunchKernelGGL(dcopy_kernel<uint4>, dim3(grid), dim3(256), 0, s, static_cast<uint4 *>(dst),
+                       static_cast<const uint4 *>(src), (int64_t)(bytes / 16));
+  } else if (a % 4 == 0 && bytes % 4 == 0) {
+    hipLaunchKernelGGL(dcopy_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, static_cast<uint32_t *>(dst),
+                       static_cast<const uint32_t *>(src), (int64_t)(bytes / 4));
+  } else {
+    hipLaunchKernelGGL(dcopy_kernel<uint8_t>, dim3(grid), dim3(256), 0, s, static_cast<uint8_t *>(dst),
+                       static_cast<const uint8_t *>(src), (int64_t)bytes);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -5;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void loss_kernel(T *lam_u, const T *y, int64_t n, double *partials) {
   __shared__ double red[kRedThreads];

@@ -30,6 +30,7 @@
 #include <map>
 
 #include "launch.hpp"
+#include "aux.hpp"
 #include "plan.hpp"
 
 namespace so2dr {
@@ -213,12 +214,19 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
       case SO2DR_OP_RS_WRITE: {
         const size_t n = (size_t)(op.z1 - op.z0) * pb;
         char *pool = P.rs_pool() + (size_t)op.pool_off * pb;
+        // a copy kernel on the compute stream, not the runtime's copy path,
+        // which may hand device copies to a DMA engine the host copies use
+        int crc;
         if (op.kind == SO2DR_OP_RS_READ) {
           char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
-          HIPCHK(hipMemcpyAsync(dst, pool, n, hipMemcpyDeviceToDevice, s));
+          crc = launch_dcopy(dst, pool, n, s);
         } else {
           const char *src = P.slot_buf(op.slot, op.buf_in) + (size_t)(op.z0 - op.buf_z0) * pb;
-          HIPCHK(hipMemcpyAsync(pool, src, n, hipMemcpyDeviceToDevice, s));
+          crc = launch_dcopy(pool, src, n, s);
+        }
+        if (crc) {
+          set_error("region-sharing copy kernel launch failed");
+          return SO2DR_E_HIP;
         }
         HIPCHK(hipEventRecord(P.ev_rs[rs_k], s));
         last_on_slot[op.pool_off] = rs_k++;
