@@ -106,7 +106,8 @@ typedef struct {
   int slot_planes;            /* planes in one slot buffer */
   int max_k_on;               /* deepest fused kernel built for this stencil */
   size_t workspace_bytes;     /* everything the plan uses; <= budget */
-  size_t slot_bytes;          /* one slot: two ping-pong buffers (five with the adjoint) */
+  size_t slot_bytes;          /* one slot: two ping-pong buffers (one when lean); an adjoint
+                                 plan adds three buffers shared by all slots */
   size_t rs_bytes;            /* region-sharing buffer */
   size_t scratch_bytes;       /* reduction scratch (adjoint) */
   int lean;                   /* 1: one buffer per slot, kernels in shifted sub-blocks */

@@ -146,7 +146,9 @@ static int loss_pass(Plan &P, AdjCtx &C, void *lam_host, const void *y_host, so2
 // lambda_{t_s} in place; u_host holds u_{t_s}.
 static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host, int kp,
                          so2dr_stats *S) {
-  enum { U0 = 0, UA = 1, UB = 2, LA = 3, LB = 4 };
+  // per slot: round-start u and lambda; shared: u recompute pair, lambda's
+  // second buffer
+  enum { U0 = 0, LA = 1, UA = 2, UB = 3, LB = 4 };
   const size_t pb = P.plane_bytes();
   const int64_t h = 2 * (int64_t)P.r * kp;
   ARC(ensure(P.ev_h2d, P.d));
@@ -239,9 +241,17 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
       S->kernel_launches += 1;
       std::swap(lcur, lnext);
     }
-    AHIP(hipEventRecord(P.ev_comp[i], s));
-    // copy-out of lambda_{t_s} over the chunk's output planes, in place
+    // copy-out of lambda_{t_s} over the chunk's output planes, in place, from
+    // the slot's own buffer: the shared one is the next chunk's
     const int64_t o0 = area_lo(P, i, kp, kp), o1 = area_hi(P, i, kp, kp);
+    if (lcur != LA) {
+      if (launch_dcopy(at(LA, o0), at(lcur, o0), (size_t)(o1 - o0) * pb, s)) {
+        set_error("adjoint copy kernel launch failed");
+        return SO2DR_E_HIP;
+      }
+      lcur = LA;
+    }
+    AHIP(hipEventRecord(P.ev_comp[i], s));
     AHIP(hipStreamWaitEvent(C.s_out, P.ev_comp[i], 0));
     AHIP(hipMemcpyAsync(static_cast<char *>(lam_host) + (size_t)o0 * pb, at(lcur, o0), (size_t)(o1 - o0) * pb,
                         hipMemcpyDeviceToHost, C.s_out));

@@ -66,15 +66,21 @@ __global__ __launch_bounds__(256) void loss_kernel(T *lam_u, const T *y, int64_t
   if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
-// acc[k] += sum_b partials[b * np + k], one lane per k, blocks in order.
-__global__ void reduce_partials(const double *partials, int nb, int np, double *acc) {
-  const int k = threadIdx.x;
-  if (k >= np) return;
+// acc[k] += sum_b partials[b * np + k]: one workgroup per k; lane t sums
+// b = t, t + 256, ... in order, then a fixed tree -- the same order every run.
+__global__ __launch_bounds__(256) void reduce_partials(const double *partials, int nb, int np, double *acc) {
+  __shared__ double red[kRedThreads];
+  const int k = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partials[(int64_t)b * np + k];
-  acc[k] += s;
+  for (int b = threadIdx.x; b < nb; b += kRedThreads) s += partials[(int64_t)b * np + k];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) acc[k] += t;
 }
 
+// Per workgroup, partials[block * NP + k] = sum over its cells x of
+// lam(x) u(x + o_k).  Workgroups take whole rows of the owned planes in turn
+// (row index -> plane and y once per row, uniform), lanes stride along x, so
+// loads are coalesced and no per-cell division is needed.
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void wgrad_kernel(const T *lam, const T *u, int64_t buf_z0, int nx,
                                                     int ny, int per_x, int per_y, int64_t n_axis,
@@ -85,27 +91,28 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const T *lam, const T *u, in
 #pragma unroll
   for (int k = 0; k < NP; ++k) acc[k] = 0.0;
   const int64_t plane = (int64_t)nx * ny;
-  const int64_t n = (z1 - z0) * plane;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const int64_t z = z0 + i / plane;
-    const int64_t rem = i % plane;
-    const int y = (int)(rem / nx), x = (int)(rem % nx);
-    const double l = to_d(lam[(z - buf_z0) * plane + rem]);
+  const int64_t nrows = (z1 - z0) * ny;
+  for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
+    const int64_t z = z0 + row / ny;
+    const int y = (int)(row % ny);
+    const T *lrow = lam + (z - buf_z0) * plane + (int64_t)y * nx;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+      const double l = to_d(lrow[x]);
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int64_t zz = z + o.dz[k];
-      int yy = y + o.dy[k], xx = x + o.dx[k];
-      if (zz < 0 || zz >= n_axis) continue;
-      if (xx < 0 || xx >= nx) {
-        if (!per_x) continue;
-        xx = xx < 0 ? xx + nx : xx - nx;
+      for (int k = 0; k < NP; ++k) {
+        const int64_t zz = z + o.dz[k];
+        int yy = y + o.dy[k], xx = x + o.dx[k];
+        if (zz < 0 || zz >= n_axis) continue;
+        if (xx < 0 || xx >= nx) {
+          if (!per_x) continue;
+          xx = xx < 0 ? xx + nx : xx - nx;
+        }
+        if (yy < 0 || yy >= ny) {
+          if (!per_y) continue;
+          yy = yy < 0 ? yy + ny : yy - ny;
+        }
+        acc[k] += l * to_d(u[(zz - buf_z0) * plane + (int64_t)yy * nx + xx]);
       }
-      if (yy < 0 || yy >= ny) {
-        if (!per_y) continue;
-        yy = yy < 0 ? yy + ny : yy - ny;
-      }
-      acc[k] += l * to_d(u[(zz - buf_z0) * plane + (int64_t)yy * nx + xx]);
     }
   }
 #pragma unroll
@@ -119,7 +126,7 @@ template <typename T>
 static int loss_t(void *lam_u, const void *y, int64_t n, double *partials, double *acc, hipStream_t s) {
   hipLaunchKernelGGL(loss_kernel<T>, dim3(kRedWgs), dim3(kRedThreads), 0, s, static_cast<T *>(lam_u),
                      static_cast<const T *>(y), n, partials);
-  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(64), 0, s, partials, kRedWgs, 1, acc);
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kRedThreads), 0, s, partials, kRedWgs, 1, acc);
   return hipGetLastError() == hipSuccess ? 0 : SO2DR_E_HIP;
 }
 
@@ -140,7 +147,7 @@ static int wgrad_np(const void *lam, const void *u, int64_t buf_z0, int nx, int 
   hipLaunchKernelGGL((wgrad_kernel<T, NP>), dim3(kRedWgs), dim3(kRedThreads), 0, s,
                      static_cast<const T *>(lam), static_cast<const T *>(u), buf_z0, nx, ny, per_x,
                      per_y, n_axis, z0, z1, o, partials);
-  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(128), 0, s, partials, kRedWgs, NP, acc);
+  hipLaunchKernelGGL(reduce_partials, dim3(NP), dim3(kRedThreads), 0, s, partials, kRedWgs, NP, acc);
   return hipGetLastError() == hipSuccess ? 0 : SO2DR_E_HIP;
 }
 

@@ -28,7 +28,8 @@ struct Plan {
   size_t buf_bytes = 0;            // one ping-pong buffer (256-aligned)
   size_t rs_bytes = 0, scratch_bytes = 0, workspace = 0, budget = 0;
   bool adjoint = false;
-  int bufs_per_slot = 2;           // 2 ping-pong buffers; 5 when the adjoint is planned
+  int bufs_per_slot = 2;           // 2 ping-pong buffers (1 in a lean plan)
+  int shared_bufs = 0;             // adjoint: working buffers the compute stream shares
   bool resreu = false;             // comparison method: per-step sharing, single-step kernels
   int ras = 0;                     // 16-bit storage rounded only where a launch stores
   bool lean = false;               // 1 buffer per slot, kernels split into shifted sub-blocks
@@ -45,11 +46,16 @@ struct Plan {
   ~Plan();
 
   size_t plane_bytes() const { return (size_t)plane * elem; }
+  // buffer `which` of a slot; indices from bufs_per_slot on name the shared
+  // working buffers, the same for every slot
   char *slot_buf(int slot, int which) const {
+    if (which >= bufs_per_slot)
+      return arena + ((size_t)n_slots * bufs_per_slot + (size_t)(which - bufs_per_slot)) * buf_bytes;
     return arena + ((size_t)slot * bufs_per_slot + (size_t)which) * buf_bytes;
   }
   char *rs_pool(int which = 0) const {
-    return arena + (size_t)n_slots * bufs_per_slot * buf_bytes + (size_t)which * rs_bytes;
+    return arena + ((size_t)n_slots * bufs_per_slot + (size_t)shared_bufs) * buf_bytes +
+           (size_t)which * rs_bytes;
   }
   int n_rs() const { return adjoint ? 2 : 1; }
   char *scratch() const { return rs_pool(0) + (size_t)n_rs() * rs_bytes; }

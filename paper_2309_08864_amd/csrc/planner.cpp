@@ -274,13 +274,16 @@ static size_t plan_bytes(Plan &P, int d, int slots, bool lean = false) {
   P.buf_bytes = align256((size_t)sp * P.plane_bytes());
   P.rs_bytes = align256((size_t)halo * P.plane_bytes());
   P.n_slots = slots;
-  // adjoint: per slot the round-start state, a recompute pair and the
-  // adjoint pair; a second region-sharing buffer for the adjoint field; FP64
+  // adjoint: per slot the round-start state and the adjoint field (copied in
+  // while another slot computes), three working buffers (a recompute pair and
+  // the adjoint's second buffer) shared by all slots since one stream
+  // computes; a second region-sharing buffer for the adjoint field; FP64
   // partial sums for the loss and weight-gradient reductions
-  P.bufs_per_slot = P.adjoint ? 5 : (lean ? 1 : 2);
+  P.bufs_per_slot = lean ? 1 : 2;
+  P.shared_bufs = P.adjoint ? 3 : 0;
   P.scratch_bytes = P.adjoint ? align256(sizeof(double) * (kRedWgs * kMaxRedPts + 256)) : 0;
-  return (size_t)slots * P.bufs_per_slot * P.buf_bytes + (size_t)P.n_rs() * P.rs_bytes +
-         P.scratch_bytes;
+  return ((size_t)slots * P.bufs_per_slot + (size_t)P.shared_bufs) * P.buf_bytes +
+         (size_t)P.n_rs() * P.rs_bytes + P.scratch_bytes;
 }
 
 static bool chunks_ok(const Plan &P, int d) {
@@ -434,8 +437,8 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     if (!chosen) { set_error("no chunk count fits the device budget"); return SO2DR_E_BUDGET; }
     plan_bytes(*P, chosen, chosen_slots, lean);
   }
-  P->workspace = (size_t)P->n_slots * P->bufs_per_slot * P->buf_bytes + (size_t)P->n_rs() * P->rs_bytes +
-                 P->scratch_bytes;
+  P->workspace = ((size_t)P->n_slots * P->bufs_per_slot + (size_t)P->shared_bufs) * P->buf_bytes +
+                 (size_t)P->n_rs() * P->rs_bytes + P->scratch_bytes;
   return SO2DR_OK;
 }
 
