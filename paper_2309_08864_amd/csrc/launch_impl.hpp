@@ -159,9 +159,11 @@ int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) 
 // per row, 32-bit byte offsets within a plane, 32-bit plane indices.
 template <typename T, int VX>
 inline bool march_fits(const LaunchParams &p) {
+  // the kernels clamp loads into [max(in_lo, 0), min(in_hi, n_axis)): that
+  // range must be non-empty
   return p.nx % VX == 0 && (uint64_t)p.plane * sizeof(T) < ((uint64_t)1 << 32) &&
          p.n_axis < ((int64_t)1 << 30) && p.in_lo > -((int64_t)1 << 29) && p.buf_z0 > -((int64_t)1 << 29) &&
-         p.out_z0 > -((int64_t)1 << 29) && p.in_lo < p.in_hi;
+         p.out_z0 > -((int64_t)1 << 29) && std::max<int64_t>(p.in_lo, 0) < std::min<int64_t>(p.in_hi, p.n_axis);
 }
 
 template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1,
