@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--auto-depth", action="store_true", help="with --auto: choose the TB depth too")
     ap.add_argument("--T", type=int, default=0, help="override the workload's number of time steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-alloc", default="so2dr", choices=["so2dr", "torch"],
+                    help="allocator of the pinned host fields")
     ap.add_argument("--cpu-sample-planes", type=int, default=0)
     ap.add_argument("--compare-storage", default=None,
                     help="also run this storage type on the same input and report the "
@@ -96,6 +98,20 @@ def weights_for(wl, offs):
     raise ValueError(wl.weights)
 
 
+HOST_ALLOC = "so2dr"
+
+
+def host_empty(shape, dtype):
+    """Page-locked host tensor: from the library's allocator (the runtime's
+    own, whose copies run on the DMA engines) or, with --host-alloc torch,
+    PyTorch's pinned allocator."""
+    import torch
+    if HOST_ALLOC == "torch":
+        return torch.empty(shape, dtype=dtype, pin_memory=True)
+    from paper_2309_08864_amd import pinned_empty
+    return pinned_empty(shape, dtype)
+
+
 def draw_field(wl, dtype):
     """The workload's initial field as a pinned host tensor of `dtype`
     (float32 or float64), drawn block by block from the recipe's seed."""
@@ -104,7 +120,7 @@ def draw_field(wl, dtype):
     gen = {"uniform": workloads.uniform_into, "fourier": workloads.fourier_modes_into,
            "bump": workloads.gaussian_bump_into}[wl.init]
     shape = (wl.ny, wl.nx) if wl.ndim == 2 else (wl.nz, wl.ny, wl.nx)
-    h = torch.empty(shape, dtype=dtype, pin_memory=True)
+    h = host_empty(shape, dtype)
     gen(h.numpy(), wl.seed)
     return h
 
@@ -112,7 +128,7 @@ def draw_field(wl, dtype):
 def rounded_copy(src, dtype):
     """Pinned copy of src rounded (nearest even) to dtype, plane block by block."""
     import torch
-    h = torch.empty(src.shape, dtype=dtype, pin_memory=True)
+    h = host_empty(src.shape, dtype)
     for z0 in range(0, src.shape[0], 64):
         h[z0:z0 + 64].copy_(src[z0:z0 + 64])
     return h
@@ -153,7 +169,7 @@ def bench_adjoint(args, wl, w):
                 k_on=args.k_on, n_slots=args.slots, budget=wl.budget, bc=wl.periodic)
     u0 = draw_field(wl, torch.float32)
     wt = workloads.fp32_rounded(workloads.perturbed(w, wl.extra["target_seed"]))
-    y = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+    y = host_empty(shape, torch.float32)
     pt = Plan(weights=list(wt), **base).bind()
     t0 = time.perf_counter()
     pt.run_steps(u0, y, wl.T)
@@ -161,9 +177,9 @@ def bench_adjoint(args, wl, w):
     pt.close()
     plan = Plan(weights=list(w), adjoint=True, **base).bind()
     info = plan.info()
-    ckpt = [torch.empty(shape, dtype=torch.float32, pin_memory=True)
+    ckpt = [host_empty(shape, torch.float32)
             for _ in range(adjoint_buffers_needed(wl.T, info["tb_depth"], c))]
-    g = torch.empty(shape, dtype=torch.float32, pin_memory=True)
+    g = host_empty(shape, torch.float32)
     print(f"# adjoint plan {info}; {len(ckpt)} host checkpoint fields; forward {t_fwd:.2f} s",
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -193,7 +209,7 @@ def bench_adjoint(args, wl, w):
                         f"{info['n_chunks']} chunks, k_on={info['k_on']}, "
                         f"budget {wl.budget / 2**30:g} GiB",
             "cells": wl.cells, "T": wl.T, "workspace_bytes": info["workspace_bytes"],
-            "host_checkpoint_fields": len(ckpt)},
+            "host_checkpoint_fields": len(ckpt), "host_alloc": args.host_alloc},
         "forward_GCells": round(wl.cells * wl.T / t_fwd / 1e9, 3),
         "gradient_over_forward_time": round(elapsed / args.steps / t_fwd, 3),
         "link": {"achieved_GBps": round(link / elapsed / 1e9, 2), "peak_GBps": LINK_PEAK_GBPS},
@@ -213,6 +229,8 @@ def main():
     import torch
     import workloads
     from paper_2309_08864_amd import Plan, stencil_offsets
+    global HOST_ALLOC
+    HOST_ALLOC = args.host_alloc
 
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -307,6 +325,7 @@ def main():
             "redundant_fraction": round(info["redundant_fraction"], 4),
             "method": args.method, "lean": info["lean"], "rounding": args.rounding,
             "planned_by": "cost model" if args.auto else "given",
+            "host_alloc": args.host_alloc,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -220,6 +220,21 @@ int so2dr_adjoint_run(struct so2dr_plan *plan, const void *host_u0, const void *
                       void *host_grad_u0, double *grad_w, double *loss, int ckpt_every,
                       void *const *host_ckpt, int n_ckpt, so2dr_stats *st);
 
+/* Page-locked host memory for the fields that runs read and write (host
+ * memory management; not in the paper).  *ptr receives `bytes` bytes from
+ * the HIP runtime's own page-locked allocator (default flags), 4096-byte
+ * aligned and owned by the caller until so2dr_host_free; bytes == 0 gives
+ * *ptr = NULL.  The runtime moves such memory to and from HBM on its DMA
+ * engines.  Page-locked memory from other allocators may instead be copied
+ * by runtime copy kernels (measured on MI355X for PyTorch's pinned tensors,
+ * HBM -> host direction), which take compute units from the stencil kernels.
+ * Errors: E_INVALID (null ptr), E_HIP (allocation failed; *ptr = NULL). */
+int so2dr_host_alloc(size_t bytes, void **ptr);
+
+/* Release memory from so2dr_host_alloc; NULL is a no-op.  Not while a run
+ * that uses it is in flight.  Errors: E_HIP. */
+int so2dr_host_free(void *ptr);
+
 /* Machine figures for the cost model (no counterpart in the paper, which
  * leaves the automatic choice of chunk count and TB depth to future work,
  * Sec. IV-C and VII).  Rates in GB/s (1e9 bytes) and G cell-updates/s. */

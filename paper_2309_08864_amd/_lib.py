@@ -22,7 +22,7 @@ EXPORTS = ["so2dr_plan_create", "so2dr_plan_destroy", "so2dr_plan_get_info",
            "so2dr_plan_workspace_bytes", "so2dr_plan_get_ops", "so2dr_plan_bind",
            "so2dr_plan_set_timing", "so2dr_run", "so2dr_run_steps", "so2dr_adjoint_run",
            "so2dr_last_error", "so2dr_version", "so2dr_machine_default", "so2dr_plan_predict",
-           "so2dr_plan_suggest"]
+           "so2dr_plan_suggest", "so2dr_host_alloc", "so2dr_host_free"]
 
 
 class Desc(ctypes.Structure):
@@ -105,12 +105,15 @@ def lib():
                                          ctypes.POINTER(ctypes.c_double)]
         L.so2dr_plan_suggest.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(Machine),
                                          ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_double)]
+        L.so2dr_host_alloc.argtypes = [ctypes.c_size_t, ctypes.POINTER(vp)]
+        L.so2dr_host_free.argtypes = [vp]
         L.so2dr_last_error.restype = ctypes.c_char_p
         L.so2dr_version.restype = ctypes.c_char_p
         for f in ("so2dr_plan_create", "so2dr_plan_get_info", "so2dr_plan_workspace_bytes",
                   "so2dr_plan_get_ops", "so2dr_plan_bind", "so2dr_plan_set_timing", "so2dr_run",
                   "so2dr_run_steps", "so2dr_adjoint_run", "so2dr_machine_default",
-                  "so2dr_plan_predict", "so2dr_plan_suggest"):
+                  "so2dr_plan_predict", "so2dr_plan_suggest", "so2dr_host_alloc",
+                  "so2dr_host_free"):
             getattr(L, f).restype = i32
         _LIB = L
     return _LIB

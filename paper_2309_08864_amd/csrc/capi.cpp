@@ -227,6 +227,34 @@ int so2dr_adjoint_run(so2dr_plan *plan, const void *host_u0, const void *host_ta
   GUARD_END
 }
 
+int so2dr_host_alloc(size_t bytes, void **ptr) {
+  if (!ptr) {
+    set_error("null output pointer");
+    return SO2DR_E_INVALID;
+  }
+  *ptr = nullptr;
+  if (bytes == 0) return SO2DR_OK;
+  void *p = nullptr;
+  const hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_error(std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    return SO2DR_E_HIP;
+  }
+  *ptr = p;
+  set_error("");
+  return SO2DR_OK;
+}
+
+int so2dr_host_free(void *ptr) {
+  if (!ptr) return SO2DR_OK;
+  const hipError_t e = hipHostFree(ptr);
+  if (e != hipSuccess) {
+    set_error(std::string("hipHostFree: ") + hipGetErrorString(e));
+    return SO2DR_E_HIP;
+  }
+  return SO2DR_OK;
+}
+
 const char *so2dr_last_error(void) { return so2dr::g_err.c_str(); }
 
 const char *so2dr_version(void) { return "so2dr-mi355x 0.1 (gfx950)"; }

@@ -1,6 +1,7 @@
 // launch_impl.hpp -- shared by the kernels_<type>.hip files: builds the
 // argument block, sizes the grid and launches one tb_kernel instantiation.
 #pragma once
+#include <atomic>
 #include <algorithm>
 #include <string>
 
@@ -42,12 +43,35 @@ namespace so2dr {
 constexpr int64_t kTargetWgs = SO2DR_TARGET_WGS;
 constexpr int64_t kMinSegPlanes = SO2DR_MIN_SEG;
 
-// Segmenting of the cut axis shared by both kernel families.
-inline void plan_segments(int64_t span, int64_t tiles, int64_t *zseg, int *nseg) {
-  int64_t n = std::max<int64_t>(1, (kTargetWgs + tiles - 1) / tiles);
+// Segmenting of the cut axis shared by both kernel families: `target`
+// workgroups, never segments shorter than kMinSegPlanes.
+inline void plan_segments(int64_t span, int64_t tiles, int64_t *zseg, int *nseg,
+                          int64_t target = kTargetWgs) {
+  int64_t n = std::max<int64_t>(1, (target + tiles - 1) / tiles);
   n = std::min<int64_t>(n, std::max<int64_t>(1, span / kMinSegPlanes));
   *zseg = (span + n - 1) / n;
   *nseg = (int)((span + *zseg - 1) / *zseg);
+}
+
+// Workgroups of `kernel` (block of `threads`) that the current device holds
+// at once: resident workgroups per CU times CUs; 0 if the runtime cannot
+// tell.  Per-CU residency depends only on the kernel, so it is asked once
+// per kernel; the CU count once per device.
+inline int64_t resident_wgs(const void *kernel, int threads, std::atomic<int> *per_cu_cache) {
+  int per_cu = per_cu_cache->load(std::memory_order_relaxed);
+  if (per_cu < 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) per_cu = 0;
+    per_cu_cache->store(per_cu, std::memory_order_relaxed);
+  }
+  static std::atomic<int> cu_count[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  int cus = cu_count[dev].load(std::memory_order_relaxed);
+  if (cus <= 0) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    cu_count[dev].store(cus, std::memory_order_relaxed);
+  }
+  return (int64_t)per_cu * cus;
 }
 
 template <typename T, int NDIM, bool BOX, int R, int KL, bool RAS = false>
@@ -200,7 +224,13 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
   a.nty = (int)((p.ny + G::OY - 1) / G::OY);
   const int64_t span = p.out_hi - p.out_lo;
   if (span <= 0) return 0;
-  plan_segments(span, (int64_t)a.ntx * a.nty, &a.zseg, &a.nseg);
+  // About 1.5 workgroups per resident slot: measured on MI355X over
+  // 2048x1024x80 chunks, fewer leave the last wave of workgroups short and
+  // more re-read 2 KL R planes per extra segment.
+  static std::atomic<int> per_cu{-1};
+  const void *kfn = (const void *)march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE, RAS>;
+  const int64_t slots = resident_wgs(kfn, NW * 64, &per_cu);
+  plan_segments(span, (int64_t)a.ntx * a.nty, &a.zseg, &a.nseg, slots > 0 ? slots * 3 / 2 : kTargetWgs);
   const int64_t nwg = (int64_t)a.ntx * a.nty * a.nseg;
   if (nwg > 0x7fffffff) {
     if (msg) *msg = "grid too large for one launch";
@@ -276,13 +306,16 @@ constexpr size_t march_lds() {
 
 // Kernel choice per depth, from measurements on MI355X (one launch over a
 // 2048x1024x80 FP32 chunk; all variants give identical bits):
-//   * single-step launches, and two fused steps of the radius-1 star, run
-//     best with 1 KiB rows (4 cells per lane, 16 waves of 2 rows):
-//     0.31-0.32 ms, 4.1-4.3 TB/s;
-//   * deeper fusion, the 13-point star and the 27-point box run best with
-//     512-byte rows (2 cells per lane, 8 waves of 4 rows, two workgroups per
-//     CU): 7-point at 3 levels 1.22 T updates/s (0.38 ms), 27-point at 2
-//     levels 0.68 T updates/s;
+//   * single-step launches run best with 1 KiB rows (4 cells per lane, 16
+//     waves of 2 rows): 0.32 ms, 4.1 TB/s;
+//   * two fused steps of the radius-1 star: 1 KiB rows, 8 waves of 4 rows
+//     (0.28 ms, 4.6 TB/s);
+//   * three fused steps of the radius-1 star and two of the radius-2 star:
+//     512-byte rows, 8 waves of 6 rows (taller tiles re-read fewer halo rows;
+//     1.37 and 0.82 T updates/s);
+//   * other deeper fusion and the 27-point box: 512-byte rows, 8 waves of 4
+//     rows (27-point at 2 levels 0.70 T updates/s);
+//   (the taller shapes hold FP32 sums only: FP64 keeps the 4-row tiles)
 //   * grids whose row length is not a multiple of the cells per lane fall
 //     back to the register-column kernel, 2D grids and whatever does not fit
 //     to the LDS-plane kernel.
@@ -297,13 +330,21 @@ int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
     if (march_fits<T, 4>(p)) return launch_march2d_one<T, BOX, R, KL, 4, 2, rot, RAS>(p, s, msg);
   }
   if constexpr (NDIM == 3 && SO2DR_MARCH_KERNEL) {
-    constexpr bool wide = (KL == 1 || (KL == 2 && !BOX && R == 1)) && march_lds<A, KL, 16, R, 4, 2>() <= kLdsMax;
+    constexpr bool wide = KL == 1 && march_lds<A, KL, 16, R, 4, 2>() <= kLdsMax;
+    constexpr bool a32 = sizeof(A) == 4;
+    constexpr bool square = a32 && !BOX && R == 1 && KL == 2;
+    constexpr bool tall = a32 && !BOX && ((R == 1 && KL == 3) || (R == 2 && KL == 2));
     constexpr int HB = march_lds<A, KL, 8, R, 2, 2>() <= 65536 ? 2 : 1;
     if constexpr (wide) {
       if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 16, 2, 4, 2, 2, 1, RAS>(p, s, msg);
-    } else if constexpr (march_lds<A, KL, 8, R, 2, HB>() <= kLdsMax && 2 * ((KL * R + 1) / 2) < 32 &&
-                         4 >= R && 32 > 2 * KL * R) {
-      if (march_fits<T, 2>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 2, HB, 2, 1, RAS>(p, s, msg);
+    } else {
+      if constexpr (square)
+        if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 4, 2, 2, 1, RAS>(p, s, msg);
+      if constexpr (tall)
+        if (march_fits<T, 2>(p)) return launch_march_one<T, BOX, R, KL, 8, 6, 2, 2, 2, 1, RAS>(p, s, msg);
+      if constexpr (march_lds<A, KL, 8, R, 2, HB>() <= kLdsMax && 2 * ((KL * R + 1) / 2) < 32 &&
+                    4 >= R && 32 > 2 * KL * R)
+        if (march_fits<T, 2>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 2, HB, 2, 1, RAS>(p, s, msg);
     }
   }
   constexpr size_t lds1 = sizeof(A) * KL * 1 * 16 * 2 * R * 64 * 4;

@@ -32,9 +32,9 @@ constexpr double kRateF32[8][8] = {
     {562, 819, 810, 795, 0, 0, 0, 0},                 // 2D box r2
     {426, 408, 390, 368, 0, 0, 0, 0},                 // 2D box r3
     {233, 222, 206, 191, 0, 0, 0, 0},                 // 2D box r4
-    {527, 1013, 1220, 1215, 0, 0, 0, 0},              // 3D star r1
-    {511, 643, 0, 0, 0, 0, 0, 0},                     // 3D star r2
-    {507, 683, 622, 560, 0, 0, 0, 0},                 // 3D box r1
+    {527, 1098, 1367, 1239, 0, 0, 0, 0},              // 3D star r1
+    {539, 801, 0, 0, 0, 0, 0, 0},                     // 3D star r2
+    {496, 694, 649, 528, 0, 0, 0, 0},                 // 3D box r1
 };
 
 struct Sim {

@@ -138,6 +138,37 @@ class Plan:
             pass
 
 
+class _HostBlock:
+    """Page-locked bytes from so2dr_host_alloc, released when the last array
+    viewing them is collected."""
+
+    def __init__(self, nbytes):
+        p = ctypes.c_void_p()
+        check(lib().so2dr_host_alloc(nbytes, ctypes.byref(p)))
+        self.ptr = p.value
+        self.__array_interface__ = {"shape": (nbytes,), "typestr": "|u1",
+                                    "data": (self.ptr, False), "version": 3}
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().so2dr_host_free(ctypes.c_void_p(self.ptr))
+            self.ptr = None
+
+
+def pinned_empty(shape, dtype):
+    """Uninitialised CPU tensor of `shape` and torch `dtype` in page-locked
+    memory from the HIP runtime's own allocator (so2dr_host_alloc): its
+    copies to and from HBM run on the DMA engines, leaving the compute units
+    to the stencil kernels."""
+    import torch
+    shape = tuple(int(n) for n in (shape if isinstance(shape, (tuple, list)) else (shape,)))
+    n = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
+    if n == 0:
+        return torch.empty(shape, dtype=dtype)
+    raw = torch.from_numpy(np.asarray(_HostBlock(n)))
+    return raw.view(dtype).view(shape)
+
+
 def _make_desc(*, ndim, nx, ny, nz, shape, radius, weights, T, tb_depth, n_chunks, k_on, n_slots,
                budget, storage, bc, adjoint, method, rounding):
     w = (ctypes.c_double * len(weights))(*[float(x) for x in weights])
@@ -210,9 +241,9 @@ def _adjoint(self, u0, target, ckpt_every, ckpt=None, grad_u0=None):
     self._check_host(target)
     need = adjoint_buffers_needed(self._T, info["tb_depth"], ckpt_every)
     if ckpt is None:
-        ckpt = [torch.empty(u0.shape, dtype=u0.dtype, pin_memory=True) for _ in range(need)]
+        ckpt = [pinned_empty(u0.shape, u0.dtype) for _ in range(need)]
     if grad_u0 is None:
-        grad_u0 = torch.empty(u0.shape, dtype=u0.dtype, pin_memory=True)
+        grad_u0 = pinned_empty(u0.shape, u0.dtype)
     arr = (ctypes.c_void_p * max(1, len(ckpt)))(*[t.data_ptr() for t in ckpt])
     gw = (ctypes.c_double * self._nw)()
     loss = ctypes.c_double()

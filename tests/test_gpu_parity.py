@@ -174,6 +174,34 @@ def test_out_of_place_steps():
     assert rel_l2(full.double().numpy(), ref9) <= 1e-5
 
 
+def test_library_pinned_host_fields():
+    """Fields in so2dr_host_alloc memory (DMA-engine copies) give the same
+    bits as fields in PyTorch's pinned memory, in place and out of place, for
+    a 4-byte and a 2-byte storage type; freeing happens when the tensor goes."""
+    import gc
+    from paper_2309_08864_amd import Plan, pinned_empty
+    rng = np.random.default_rng(67)
+    for ndim, shape, r, storage in [(3, "star", 1, "f32"), (2, "star", 1, "bf16")]:
+        offs = _offsets(ndim, shape, r)
+        w = _weights(offs, rng)
+        kw = _kwargs(ndim, shape, r, w, T=9, K=4, d=3, k_on=2, storage=storage)
+        u0 = to_storage(rng.random(np_shape(ndim, *_dims(ndim))), storage)
+        ref, _, _ = gpu_run(kw, u0)
+        p = Plan(**kw)
+        p.bind()
+        h = pinned_empty(u0.shape, u0.dtype)
+        h.copy_(u0)
+        out = pinned_empty(u0.shape, u0.dtype)
+        p.run_steps(h, out, 9)
+        assert torch.equal(out, ref)
+        p.run(h)
+        assert torch.equal(h, ref)
+        p.close()
+        del h, out
+        gc.collect()
+    assert pinned_empty((0, 5), torch.float32).numel() == 0
+
+
 def test_edge_cases():
     """Tiny grids (smaller than one tile), a single plane per chunk of the
     last chunk, T = 1, nx = 1 and chunks of exactly 2 r K planes."""

@@ -217,6 +217,17 @@ def test_error_paths():
         p.run(torch.zeros(64 * 16 * 16))
 
 
+def test_host_alloc_argument_paths():
+    """so2dr_host_alloc / so2dr_host_free paths that make no HIP call."""
+    import ctypes
+    from paper_2309_08864_amd._lib import lib
+    L = lib()
+    assert L.so2dr_host_alloc(16, None) == -1                   # null output: E_INVALID
+    p = ctypes.c_void_p(1234)
+    assert L.so2dr_host_alloc(0, ctypes.byref(p)) == 0 and p.value is None
+    assert L.so2dr_host_free(None) == 0
+
+
 # ------------------------------------------------------------------ simulator
 def _np_step(win, offs, w, per_x, per_y):
     """One step on a window of planes: win is (planes, ny, nx) FP64 of level
