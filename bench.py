@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--host-alloc", default="so2dr", choices=["so2dr", "torch"],
                     help="allocator of the pinned host fields")
+    ap.add_argument("--copy-engine", default="auto", choices=["auto", "dma", "kernel"],
+                    help="what moves chunks between host and HBM")
     ap.add_argument("--cpu-sample-planes", type=int, default=0)
     ap.add_argument("--compare-storage", default=None,
                     help="also run this storage type on the same input and report the "
@@ -166,7 +168,8 @@ def bench_adjoint(args, wl, w):
     shape = (wl.nz, wl.ny, wl.nx)
     base = dict(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
                 T=wl.T, tb_depth=args.tb_depth or wl.tb_depth, n_chunks=args.chunks or wl.n_chunks,
-                k_on=args.k_on, n_slots=args.slots, budget=wl.budget, bc=wl.periodic)
+                k_on=args.k_on, n_slots=args.slots, budget=wl.budget, bc=wl.periodic,
+                copy_engine=args.copy_engine)
     u0 = draw_field(wl, torch.float32)
     wt = workloads.fp32_rounded(workloads.perturbed(w, wl.extra["target_seed"]))
     y = host_empty(shape, torch.float32)
@@ -209,7 +212,8 @@ def bench_adjoint(args, wl, w):
                         f"{info['n_chunks']} chunks, k_on={info['k_on']}, "
                         f"budget {wl.budget / 2**30:g} GiB",
             "cells": wl.cells, "T": wl.T, "workspace_bytes": info["workspace_bytes"],
-            "host_checkpoint_fields": len(ckpt), "host_alloc": args.host_alloc},
+            "host_checkpoint_fields": len(ckpt), "host_alloc": args.host_alloc,
+            "copy_engine": {1: "dma", 2: "kernel"}[info["copy_engine"]]},
         "forward_GCells": round(wl.cells * wl.T / t_fwd / 1e9, 3),
         "gradient_over_forward_time": round(elapsed / args.steps / t_fwd, 3),
         "link": {"achieved_GBps": round(link / elapsed / 1e9, 2), "peak_GBps": LINK_PEAK_GBPS},
@@ -258,12 +262,13 @@ def main():
                         radius=wl.radius, weights=list(w), T=wl.T,
                         tb_depth=0 if args.auto_depth else K, n_chunks=args.chunks,
                         k_on=args.k_on, n_slots=args.slots, budget=wl.budget, storage=storage,
-                        bc=wl.periodic, method=args.method, rounding=args.rounding)
+                        bc=wl.periodic, method=args.method, rounding=args.rounding,
+                        copy_engine=args.copy_engine)
         K, d, args.k_on, args.slots = kw["tb_depth"], kw["n_chunks"], kw["k_on"], kw["n_slots"]
     plan = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
                 weights=list(w), T=wl.T, tb_depth=K, n_chunks=d, k_on=args.k_on,
                 n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic,
-                method=args.method, rounding=args.rounding)
+                method=args.method, rounding=args.rounding, copy_engine=args.copy_engine)
     info = plan.info()
     predicted_ms = plan.predict()
     plan.bind()
@@ -326,6 +331,7 @@ def main():
             "method": args.method, "lean": info["lean"], "rounding": args.rounding,
             "planned_by": "cost model" if args.auto else "given",
             "host_alloc": args.host_alloc,
+            "copy_engine": {1: "dma", 2: "kernel"}[info["copy_engine"]],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -361,7 +367,7 @@ def main():
         plan2 = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
                      weights=list(w), T=wl.T, tb_depth=K, n_chunks=d, k_on=args.k_on,
                      n_slots=args.slots, budget=wl.budget, storage=storage, bc=wl.periodic,
-                     rounding=args.rounding).bind()
+                     rounding=args.rounding, copy_engine=args.copy_engine).bind()
         plan2.run(h)
         plan2.close()
         hm = h
@@ -371,7 +377,7 @@ def main():
         ref_plan = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape,
                         radius=wl.radius, weights=list(wr), T=wl.T, tb_depth=K, n_chunks=d,
                         n_slots=args.slots, budget=wl.budget, storage=args.compare_storage,
-                        bc=wl.periodic).bind()
+                        bc=wl.periodic, copy_engine=args.copy_engine).bind()
         hr = master if master.dtype == cdt else rounded_copy(master, cdt)
         t1 = time.perf_counter()
         ref_plan.run(hr)

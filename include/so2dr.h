@@ -75,6 +75,21 @@ typedef enum { SO2DR_METHOD_SO2DR = 0, SO2DR_METHOD_RESREU = 1 } so2dr_method;
  *     tb_depth is a multiple of k_on. */
 typedef enum { SO2DR_ROUND_EVERY_STEP = 0, SO2DR_ROUND_AT_STORE = 1 } so2dr_rounding;
 
+/* What carries the host <-> HBM copies (no counterpart in the paper, whose
+ * copies are cudaMemcpyAsync).
+ *   SO2DR_COPY_DMA: hipMemcpyAsync, the runtime's DMA engines.  Fastest for
+ *     large copies (97 GB/s both directions together on MI355X); with many
+ *     small copies enqueued at once its rate measured erratic, down to a
+ *     third of that.
+ *   SO2DR_COPY_KERNEL: a copy kernel of 64 workgroups per copy reads or
+ *     writes the page-locked host array through its device mapping (about
+ *     85 GB/s both directions together, independent of the copy size); the
+ *     host array must be one page-locked allocation mapped into the device,
+ *     else the run fails with E_NOT_PINNED.
+ *   SO2DR_COPY_AUTO: copy kernels when the plan's largest chunk copy is
+ *     below a measured threshold and both host arrays are mapped, else DMA. */
+typedef enum { SO2DR_COPY_AUTO = 0, SO2DR_COPY_DMA = 1, SO2DR_COPY_KERNEL = 2 } so2dr_copy_engine;
+
 /* Problem and run-time configuration: the variables of the paper's Table I
  * (dim, sz, r, d, S_tot, S_TB, N_strm, C_dmem) plus the stencil itself. */
 typedef struct {
@@ -95,6 +110,7 @@ typedef struct {
   int adjoint;                /* 1: also reserve what so2dr_adjoint_run needs */
   int method;                 /* so2dr_method: SO2DR_METHOD_SO2DR (default) or _RESREU */
   int rounding;               /* an so2dr_rounding value, for 16-bit storage; 0 = every step */
+  int copy_engine;            /* an so2dr_copy_engine value; 0 = automatic */
 } so2dr_desc;
 
 /* What the planner chose (all sizes in bytes unless noted). */
@@ -116,6 +132,7 @@ typedef struct {
   double redundant_fraction;  /* recomputed / useful cell updates */
   int64_t n_ops;              /* entries in the operation schedule */
   int rounding;               /* the so2dr_rounding value in effect: EVERY_STEP unless 16-bit storage */
+  int copy_engine;            /* SO2DR_COPY_DMA or _KERNEL: what runs use when the host arrays allow */
 } so2dr_plan_info;
 
 /* One entry of the schedule the executor runs (Algorithm 1, unrolled).
@@ -225,9 +242,9 @@ int so2dr_adjoint_run(struct so2dr_plan *plan, const void *host_u0, const void *
  * the HIP runtime's own page-locked allocator (default flags), 4096-byte
  * aligned and owned by the caller until so2dr_host_free; bytes == 0 gives
  * *ptr = NULL.  The runtime moves such memory to and from HBM on its DMA
- * engines.  Page-locked memory from other allocators may instead be copied
- * by runtime copy kernels (measured on MI355X for PyTorch's pinned tensors,
- * HBM -> host direction), which take compute units from the stencil kernels.
+ * engines (SO2DR_COPY_DMA).  Page-locked memory from other allocators may
+ * instead be copied by the runtime's own copy kernels (measured on MI355X for
+ * PyTorch's pinned tensors, HBM -> host direction).
  * Errors: E_INVALID (null ptr), E_HIP (allocation failed; *ptr = NULL). */
 int so2dr_host_alloc(size_t bytes, void **ptr);
 
@@ -245,6 +262,7 @@ typedef struct {
   double launch_us;            /* fixed cost of one kernel launch */
   double gupd[8];              /* output cells x levels per second of a fused
                                   launch of 1..8 levels; 0 = not available */
+  double kcopy_gbps;           /* both directions at once with copy kernels */
 } so2dr_machine;
 
 /* Fill *m with the library's built-in figures for this plan's stencil and

@@ -15,6 +15,7 @@ DTYPES = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3}
 SHAPES = {"star": 0, "box": 1}
 METHODS = {"so2dr": 0, "resreu": 1}
 ROUNDING = {"every_step": 0, "at_store": 1}
+COPY_ENGINES = {"auto": 0, "dma": 1, "kernel": 2}
 OP_KINDS = {0: "H2D", 1: "RS_READ", 2: "RS_WRITE", 3: "KERNEL", 4: "D2H"}
 
 # Symbols the header declares; the CPU test checks each is exported.
@@ -32,13 +33,15 @@ class Desc(ctypes.Structure):
                 ("bc", ctypes.c_int * 3), ("storage", ctypes.c_int), ("T", ctypes.c_int),
                 ("n_chunks", ctypes.c_int), ("tb_depth", ctypes.c_int), ("k_on", ctypes.c_int),
                 ("n_slots", ctypes.c_int), ("device_budget_bytes", ctypes.c_size_t),
-                ("adjoint", ctypes.c_int), ("method", ctypes.c_int), ("rounding", ctypes.c_int)]
+                ("adjoint", ctypes.c_int), ("method", ctypes.c_int), ("rounding", ctypes.c_int),
+                ("copy_engine", ctypes.c_int)]
 
 
 class Machine(ctypes.Structure):
     _fields_ = [("h2d_gbps", ctypes.c_double), ("d2h_gbps", ctypes.c_double),
                 ("duplex_gbps", ctypes.c_double), ("d2d_gbps", ctypes.c_double),
-                ("launch_us", ctypes.c_double), ("gupd", ctypes.c_double * 8)]
+                ("launch_us", ctypes.c_double), ("gupd", ctypes.c_double * 8),
+                ("kcopy_gbps", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -51,7 +54,7 @@ class PlanInfo(ctypes.Structure):
                 ("scratch_bytes", ctypes.c_size_t), ("lean", ctypes.c_int),
                 ("lean_block", ctypes.c_int), ("method", ctypes.c_int),
                 ("redundant_fraction", ctypes.c_double),
-                ("n_ops", ctypes.c_int64), ("rounding", ctypes.c_int)]
+                ("n_ops", ctypes.c_int64), ("rounding", ctypes.c_int), ("copy_engine", ctypes.c_int)]
 
 
 class Op(ctypes.Structure):

@@ -103,6 +103,8 @@ static LaunchParams base_launch(const Plan &P, const double *w) {
 
 struct AdjCtx {
   hipStream_t s_in, s_out, s_comp;
+  bool kcopy = false;  // host copies by copy kernels through the host mappings
+  size_t field = 0;
   double *partials, *acc_w, *acc_loss;
   std::vector<double> wT;  // reflected weights
   RedOffsets offs;
@@ -115,14 +117,16 @@ static int loss_pass(Plan &P, AdjCtx &C, void *lam_host, const void *y_host, so2
   ARC(ensure(P.ev_h2d, P.d));
   ARC(ensure(P.ev_comp, P.d));
   ARC(ensure(P.ev_d2h, P.d));
+  char *d_lam = C.kcopy ? mapped_host(lam_host, C.field) : nullptr;
+  char *d_y = C.kcopy ? mapped_host(y_host, C.field) : nullptr;
   for (int i = 0; i < P.d; ++i) {
     const int slot = i % P.n_slots;
     const int64_t z0 = P.bnd[i], z1 = P.bnd[i + 1];
     const size_t n = (size_t)(z1 - z0) * pb;
     char *ub = P.slot_buf(slot, 0), *yb = P.slot_buf(slot, 1);
     if (i >= P.n_slots) AHIP(hipStreamWaitEvent(C.s_in, P.ev_d2h[i - P.n_slots], 0));
-    AHIP(hipMemcpyAsync(ub, static_cast<char *>(lam_host) + (size_t)z0 * pb, n, hipMemcpyHostToDevice, C.s_in));
-    AHIP(hipMemcpyAsync(yb, static_cast<const char *>(y_host) + (size_t)z0 * pb, n, hipMemcpyHostToDevice, C.s_in));
+    ARC(copy_to_device(ub, static_cast<char *>(lam_host) + (size_t)z0 * pb, n, lam_host, d_lam, C.s_in));
+    ARC(copy_to_device(yb, static_cast<const char *>(y_host) + (size_t)z0 * pb, n, y_host, d_y, C.s_in));
     AHIP(hipEventRecord(P.ev_h2d[i], C.s_in));
     AHIP(hipStreamWaitEvent(C.s_comp, P.ev_h2d[i], 0));
     if (launch_loss(P.dtype, ub, yb, (int64_t)(z1 - z0) * P.plane, C.partials, C.acc_loss, C.s_comp)) {
@@ -131,7 +135,7 @@ static int loss_pass(Plan &P, AdjCtx &C, void *lam_host, const void *y_host, so2
     }
     AHIP(hipEventRecord(P.ev_comp[i], C.s_comp));
     AHIP(hipStreamWaitEvent(C.s_out, P.ev_comp[i], 0));
-    AHIP(hipMemcpyAsync(static_cast<char *>(lam_host) + (size_t)z0 * pb, ub, n, hipMemcpyDeviceToHost, C.s_out));
+    ARC(copy_to_host(static_cast<char *>(lam_host) + (size_t)z0 * pb, ub, n, lam_host, d_lam, C.s_out));
     AHIP(hipEventRecord(P.ev_d2h[i], C.s_out));
     S->bytes_h2d += 2 * n;
     S->bytes_d2h += n;
@@ -156,6 +160,8 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
   ARC(ensure(P.ev_d2h, P.d));
   ARC(ensure(P.ev_rs, P.d));
   std::string msg;
+  char *d_u = C.kcopy ? mapped_host(u_host, C.field) : nullptr;
+  char *d_lam = C.kcopy ? mapped_host(lam_host, C.field) : nullptr;
   LaunchParams fwd = base_launch(P, P.weights.data());
   LaunchParams adj = base_launch(P, C.wT.data());
   for (int i = 0; i < P.d; ++i) {
@@ -167,10 +173,10 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
     // copy-in of the own planes of u_{t_s} and lambda_{t_e}
     if (i >= P.n_slots) AHIP(hipStreamWaitEvent(C.s_in, P.ev_d2h[i - P.n_slots], 0));
     const size_t own = (size_t)(b1 - b0) * pb;
-    AHIP(hipMemcpyAsync(at(U0, b0), static_cast<const char *>(u_host) + (size_t)b0 * pb, own,
-                        hipMemcpyHostToDevice, C.s_in));
-    AHIP(hipMemcpyAsync(at(LA, b0), static_cast<char *>(lam_host) + (size_t)b0 * pb, own,
-                        hipMemcpyHostToDevice, C.s_in));
+    ARC(copy_to_device(at(U0, b0), static_cast<const char *>(u_host) + (size_t)b0 * pb, own, u_host, d_u,
+                       C.s_in));
+    ARC(copy_to_device(at(LA, b0), static_cast<char *>(lam_host) + (size_t)b0 * pb, own, lam_host, d_lam,
+                       C.s_in));
     AHIP(hipEventRecord(P.ev_h2d[i], C.s_in));
     S->bytes_h2d += 2 * own;
     // region sharing for both fields: read the lower halo, then write the own top
@@ -179,8 +185,12 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
     if (i > 0) AHIP(hipStreamWaitEvent(s, P.ev_rs[i - 1], 0));
     for (int f = 0; f < 2; ++f) {
       const int which = f == 0 ? U0 : LA;
-      if (i > 0) AHIP(hipMemcpyAsync(at(which, b0 - h), P.rs_pool(f), (size_t)h * pb, hipMemcpyDeviceToDevice, s));
-      if (i < P.d - 1) AHIP(hipMemcpyAsync(P.rs_pool(f), at(which, b1 - h), (size_t)h * pb, hipMemcpyDeviceToDevice, s));
+      // copy kernels on the compute stream, as in the forward executor
+      if ((i > 0 && launch_dcopy(at(which, b0 - h), P.rs_pool(f), (size_t)h * pb, s)) ||
+          (i < P.d - 1 && launch_dcopy(P.rs_pool(f), at(which, b1 - h), (size_t)h * pb, s))) {
+        set_error("region-sharing copy kernel launch failed");
+        return SO2DR_E_HIP;
+      }
       S->bytes_d2d += (size_t)h * pb * ((i > 0) + (i < P.d - 1));
     }
     AHIP(hipEventRecord(P.ev_rs[i], s));
@@ -253,8 +263,8 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
     }
     AHIP(hipEventRecord(P.ev_comp[i], s));
     AHIP(hipStreamWaitEvent(C.s_out, P.ev_comp[i], 0));
-    AHIP(hipMemcpyAsync(static_cast<char *>(lam_host) + (size_t)o0 * pb, at(lcur, o0), (size_t)(o1 - o0) * pb,
-                        hipMemcpyDeviceToHost, C.s_out));
+    ARC(copy_to_host(static_cast<char *>(lam_host) + (size_t)o0 * pb, at(lcur, o0), (size_t)(o1 - o0) * pb,
+                     lam_host, d_lam, C.s_out));
     AHIP(hipEventRecord(P.ev_d2h[i], C.s_out));
     S->bytes_d2h += (size_t)(o1 - o0) * pb;
   }
@@ -301,6 +311,19 @@ int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, doub
   std::memset(&S, 0, sizeof(S));
   const auto t0 = std::chrono::steady_clock::now();
   AdjCtx C;
+  C.field = field;
+  C.kcopy = P.copy_engine == SO2DR_COPY_KERNEL;
+  if (C.kcopy) {
+    bool all = mapped_host(u0, field) && mapped_host(target, field) && mapped_host(grad_u0, field);
+    for (int j = 0; j < need; ++j) all = all && mapped_host(ckpt[j], field);
+    if (!all) {
+      if (P.copy_engine_forced) {
+        set_error("copy kernels need each host array inside one page-locked allocation mapped into the device");
+        return SO2DR_E_NOT_PINNED;
+      }
+      C.kcopy = false;
+    }
+  }
   const int ns = (int)P.streams.size();
   C.s_in = P.streams[0];
   C.s_out = ns >= 2 ? P.streams[1] : P.streams[0];

@@ -26,7 +26,8 @@ int launch_wgrad(int dtype, const void *lam, const void *u, int64_t buf_z0, int 
                  int per_x, int per_y, int64_t n_axis, int64_t z0, int64_t z1,
                  const RedOffsets &offs, int npts, double *partials, double *acc, hipStream_t s);
 
-// dst <- src, `bytes` bytes of device memory, by a copy kernel on stream s.
-int launch_dcopy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// dst <- src, `bytes` bytes of device-addressable memory, by a copy kernel
+// of `grid` workgroups on stream s.
+int launch_dcopy(void *dst, const void *src, size_t bytes, hipStream_t s, int grid = 1024);
 
 }  // namespace so2dr

@@ -35,10 +35,10 @@ __global__ __launch_bounds__(256) void dcopy_kernel(W *__restrict__ dst, const W
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-int launch_dcopy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+int launch_dcopy(void *dst, const void *src, size_t bytes, hipStream_t s, int grid) {
   if (bytes == 0) return 0;
   const uintptr_t a = (uintptr_t)dst | (uintptr_t)src;
-  const int grid = 1024;
+  grid = grid < 1 ? 1 : grid;
   if (a % 16 == 0 && bytes % 16 == 0) {
     hipLaunchKernelGGL(dcopy_kernel<uint4>, dim3(grid), dim3(256), 0, s, static_cast<uint4 *>(dst),
                        static_cast<const uint4 *>(src), (int64_t)(bytes / 16));
@@ -80,12 +80,18 @@ __global__ __launch_bounds__(256) void reduce_partials(const double *partials, i
 // Per workgroup, partials[block * NP + k] = sum over its cells x of
 // lam(x) u(x + o_k).  Workgroups take whole rows of the owned planes in turn
 // (row index -> plane and y once per row, uniform), lanes stride along x, so
-// loads are coalesced and no per-cell division is needed.
+// loads are coalesced and no per-cell division is needed.  A lane loads the
+// values of up to 4 cells of its row (x, x + 256, ...) before it accumulates any,
+// so each wave keeps several cells' loads in flight instead of one's; the
+// accumulation order per lane is unchanged (cells by increasing x, points in
+// order), and neighbours outside the grid are loaded from a clamped in-grid
+// address and not accumulated.
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void wgrad_kernel(const T *lam, const T *u, int64_t buf_z0, int nx,
                                                     int ny, int per_x, int per_y, int64_t n_axis,
                                                     int64_t z0, int64_t z1, RedOffsets o,
                                                     double *partials) {
+  constexpr int WU = NP <= 13 ? 4 : NP <= 27 ? 2 : 1;  // cells per lane in flight
   __shared__ double red[kRedThreads];
   double acc[NP];
 #pragma unroll
@@ -96,23 +102,48 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const T *lam, const T *u, in
     const int64_t z = z0 + row / ny;
     const int y = (int)(row % ny);
     const T *lrow = lam + (z - buf_z0) * plane + (int64_t)y * nx;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-      const double l = to_d(lrow[x]);
+    // per point: its row of u (clamped into the grid) and whether that row exists
+    const T *urow[NP];
+    bool row_ok[NP];
 #pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        const int64_t zz = z + o.dz[k];
-        int yy = y + o.dy[k], xx = x + o.dx[k];
-        if (zz < 0 || zz >= n_axis) continue;
-        if (xx < 0 || xx >= nx) {
-          if (!per_x) continue;
-          xx = xx < 0 ? xx + nx : xx - nx;
-        }
-        if (yy < 0 || yy >= ny) {
-          if (!per_y) continue;
-          yy = yy < 0 ? yy + ny : yy - ny;
-        }
-        acc[k] += l * to_d(u[(zz - buf_z0) * plane + (int64_t)yy * nx + xx]);
+    for (int k = 0; k < NP; ++k) {
+      int64_t zz = z + o.dz[k];
+      int yy = y + o.dy[k];
+      bool ok = zz >= 0 && zz < n_axis;
+      if (yy < 0 || yy >= ny) {
+        if (per_y) yy = yy < 0 ? yy + ny : yy - ny; else ok = false;
       }
+      zz = ok ? zz : z;
+      yy = ok ? yy : y;
+      urow[k] = u + (zz - buf_z0) * plane + (int64_t)yy * nx;
+      row_ok[k] = ok;
+    }
+    for (int xb = 0; xb < nx; xb += 256 * WU) {
+      T l[WU];
+      T v[WU][NP];
+      bool use[WU][NP];
+#pragma unroll
+      for (int j = 0; j < WU; ++j) {
+        const int x = xb + threadIdx.x + 256 * j;
+        const bool in = x < nx;
+        l[j] = lrow[in ? x : 0];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          int xx = x + o.dx[k];
+          bool ok = in && row_ok[k];
+          if (xx < 0 || xx >= nx) {
+            if (per_x) xx = xx < 0 ? xx + nx : xx - nx; else ok = false;
+          }
+          xx = ok ? xx : 0;
+          v[j][k] = urow[k][xx];
+          use[j][k] = ok;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < WU; ++j)
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+          if (use[j][k]) acc[k] += to_d(l[j]) * to_d(v[j][k]);
     }
   }
 #pragma unroll

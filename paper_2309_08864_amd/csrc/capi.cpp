@@ -102,6 +102,7 @@ int so2dr_plan_get_info(const so2dr_plan *plan, so2dr_plan_info *info) {
   const double useful = (double)P.N * (double)P.T;
   info->redundant_fraction = useful > 0 ? (double)computed / useful - 1.0 : 0.0;
   info->rounding = P.ras ? SO2DR_ROUND_AT_STORE : SO2DR_ROUND_EVERY_STEP;
+  info->copy_engine = P.copy_engine;
   return SO2DR_OK;
   GUARD_END
 }

@@ -32,6 +32,8 @@ struct Plan {
   int shared_bufs = 0;             // adjoint: working buffers the compute stream shares
   bool resreu = false;             // comparison method: per-step sharing, single-step kernels
   int ras = 0;                     // 16-bit storage rounded only where a launch stores
+  int copy_engine = SO2DR_COPY_DMA;  // host copies: DMA engines or copy kernels
+  bool copy_engine_forced = false;   // chosen by the caller, not automatically
   bool lean = false;               // 1 buffer per slot, kernels split into shifted sub-blocks
   int lean_block = 0;              // output planes per sub-block launch
   int64_t lean_extra = 0;          // spare planes below the round-start data
@@ -78,5 +80,22 @@ int make_plan(const so2dr_desc &d, Plan *out);
 size_t dtype_size(int dtype);
 int stencil_id(int ndim, int shape, int r);
 int expected_points(int ndim, int shape, int r);
+
+// Automatic copy engine: copy kernels when the largest chunk copy is below
+// this many bytes, the DMA engines otherwise.
+constexpr size_t kKernelCopyBelow = (size_t)512 << 20;
+// Workgroups of one host-copy kernel (about the link's rate per direction).
+constexpr int kHostCopyWgs = 64;
+
+// Device address of the host range [p, p + bytes) when it lies inside one
+// page-locked allocation mapped into the current device, else null.
+char *mapped_host(const void *p, size_t bytes);
+// One host <-> HBM copy of n bytes on stream s.  With dev_base (the device
+// address of host_base from mapped_host) a copy kernel moves the bytes
+// through the mapping; without, hipMemcpyAsync.  Returns 0 or SO2DR_E_HIP.
+int copy_to_device(void *dst, const void *src_host, size_t n, const void *host_base, char *dev_base,
+                   hipStream_t s);
+int copy_to_host(void *dst_host, const void *src, size_t n, const void *host_base, char *dev_base,
+                 hipStream_t s);
 
 }  // namespace so2dr

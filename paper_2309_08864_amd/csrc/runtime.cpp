@@ -84,6 +84,64 @@ int check_pinned(const void *p, size_t bytes, const char *what) {
   return SO2DR_OK;
 }
 
+char *mapped_host(const void *p, size_t bytes) {
+  if (!p || bytes == 0) return nullptr;
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess || a.type != hipMemoryTypeHost || !a.devicePointer) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  void *base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, a.devicePointer) != hipSuccess || !base) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  // the whole range must lie inside the one allocation that holds p
+  const uintptr_t d = (uintptr_t)a.devicePointer, b = (uintptr_t)base;
+  if (d < b || d - b > size || size - (d - b) < bytes) return nullptr;
+  return static_cast<char *>(a.devicePointer);
+}
+
+static bool kernel_copyable(const void *x, const void *y, size_t n) {
+  return (((uintptr_t)x | (uintptr_t)y | (uintptr_t)n) & 15) == 0;
+}
+
+int copy_to_device(void *dst, const void *src_host, size_t n, const void *host_base, char *dev_base,
+                   hipStream_t s) {
+  if (n == 0) return SO2DR_OK;
+  if (dev_base) {
+    const char *src = dev_base + (static_cast<const char *>(src_host) - static_cast<const char *>(host_base));
+    if (kernel_copyable(dst, src, n)) {
+      if (launch_dcopy(dst, src, n, s, kHostCopyWgs)) {
+        set_error("host copy kernel launch failed");
+        return SO2DR_E_HIP;
+      }
+      return SO2DR_OK;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(dst, src_host, n, hipMemcpyHostToDevice, s));
+  return SO2DR_OK;
+}
+
+int copy_to_host(void *dst_host, const void *src, size_t n, const void *host_base, char *dev_base,
+                 hipStream_t s) {
+  if (n == 0) return SO2DR_OK;
+  if (dev_base) {
+    char *dst = dev_base + (static_cast<char *>(dst_host) - static_cast<const char *>(host_base));
+    if (kernel_copyable(dst, src, n)) {
+      if (launch_dcopy(dst, src, n, s, kHostCopyWgs)) {
+        set_error("host copy kernel launch failed");
+        return SO2DR_E_HIP;
+      }
+      return SO2DR_OK;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(dst_host, src, n, hipMemcpyDeviceToHost, s));
+  return SO2DR_OK;
+}
+
 int bind_plan(Plan &P, void *arena, size_t bytes, void *const *streams, int n_streams) {
   if (!arena || (reinterpret_cast<uintptr_t>(arena) & 255)) {
     set_error("arena must be a non-null 256-byte aligned device pointer");
@@ -127,6 +185,19 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
   if (rc) return rc;
   rc = check_pinned(host_out, field, "output host array");
   if (rc) return rc;
+  // device mappings for copy kernels (null: hipMemcpyAsync)
+  char *dev_in = nullptr, *dev_out = nullptr;
+  if (P.copy_engine == SO2DR_COPY_KERNEL) {
+    dev_in = mapped_host(host_in, field);
+    dev_out = host_out == host_in ? dev_in : mapped_host(host_out, field);
+    if (!dev_in || !dev_out) {
+      if (P.copy_engine_forced) {
+        set_error("copy kernels need each host array inside one page-locked allocation mapped into the device");
+        return SO2DR_E_NOT_PINNED;
+      }
+      dev_in = dev_out = nullptr;
+    }
+  }
   so2dr_stats S;
   std::memset(&S, 0, sizeof(S));
   const auto t_start = std::chrono::steady_clock::now();
@@ -204,9 +275,11 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
     if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k], s));
     switch (op.kind) {
       case SO2DR_OP_H2D: {
-        const char *src = (op.round == 0 ? hin : hout) + (size_t)op.z0 * pb;
+        const char *base = op.round == 0 ? hin : hout;
+        char *dev = op.round == 0 ? dev_in : dev_out;
         char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
-        HIPCHK(hipMemcpyAsync(dst, src, (size_t)(op.z1 - op.z0) * pb, hipMemcpyHostToDevice, s));
+        rc = copy_to_device(dst, base + (size_t)op.z0 * pb, (size_t)(op.z1 - op.z0) * pb, base, dev, s);
+        if (rc) return rc;
         S.bytes_h2d += (uint64_t)(op.z1 - op.z0) * pb;
         break;
       }
@@ -265,8 +338,8 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
       }
       case SO2DR_OP_D2H: {
         const char *src = P.slot_buf(op.slot, op.buf_in) + (size_t)(op.z0 - op.buf_z0) * pb;
-        HIPCHK(hipMemcpyAsync(hout + (size_t)op.z0 * pb, src, (size_t)(op.z1 - op.z0) * pb,
-                              hipMemcpyDeviceToHost, s));
+        rc = copy_to_host(hout + (size_t)op.z0 * pb, src, (size_t)(op.z1 - op.z0) * pb, hout, dev_out, s);
+        if (rc) return rc;
         S.bytes_d2h += (uint64_t)(op.z1 - op.z0) * pb;
         if (op.chunk == P.d - 1) S.rounds_done = op.round + 1;
         break;

@@ -9,7 +9,7 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import DTYPES, METHODS, OP_KINDS, ROUNDING, SHAPES, check, lib
+from ._lib import COPY_ENGINES, DTYPES, METHODS, OP_KINDS, ROUNDING, SHAPES, check, lib
 
 TORCH_DTYPES = {"f32": "float32", "f64": "float64", "bf16": "bfloat16", "f16": "float16"}
 
@@ -35,11 +35,14 @@ class Plan:
     and is cut along y.  ``weights`` follows stencil_offsets' order.
     ``bc`` gives, per axis x, y, z, 0 for zero Dirichlet or 1 for periodic.
     ``rounding`` ("every_step" or "at_store") applies to BF16/F16 storage:
-    round after every step, or only where a launch stores to HBM."""
+    round after every step, or only where a launch stores to HBM.
+    ``copy_engine`` ("auto", "dma" or "kernel") picks what moves the chunks
+    between host and HBM: the runtime's DMA engines or copy kernels through
+    the host array's device mapping."""
 
     def __init__(self, *, ndim, nx, ny, nz=1, shape="star", radius=1, weights, T, tb_depth=0,
                  n_chunks=0, k_on=0, n_slots=0, budget, storage="f32", bc=(0, 0, 0),
-                 adjoint=False, method="so2dr", rounding="every_step"):
+                 adjoint=False, method="so2dr", rounding="every_step", copy_engine="auto"):
         self.storage = storage
         self.shape3 = (nz, ny, nx)
         self._T = T
@@ -47,7 +50,8 @@ class Plan:
         d, self._w = _make_desc(ndim=ndim, nx=nx, ny=ny, nz=nz, shape=shape, radius=radius,
                                 weights=weights, T=T, tb_depth=tb_depth, n_chunks=n_chunks,
                                 k_on=k_on, n_slots=n_slots, budget=budget, storage=storage,
-                                bc=bc, adjoint=adjoint, method=method, rounding=rounding)
+                                bc=bc, adjoint=adjoint, method=method, rounding=rounding,
+                                copy_engine=copy_engine)
         h = ctypes.c_void_p()
         check(lib().so2dr_plan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
@@ -170,7 +174,7 @@ def pinned_empty(shape, dtype):
 
 
 def _make_desc(*, ndim, nx, ny, nz, shape, radius, weights, T, tb_depth, n_chunks, k_on, n_slots,
-               budget, storage, bc, adjoint, method, rounding):
+               budget, storage, bc, adjoint, method, rounding, copy_engine="auto"):
     w = (ctypes.c_double * len(weights))(*[float(x) for x in weights])
     d = _lib.Desc()
     d.ndim, d.nx, d.ny, d.nz = ndim, nx, ny, nz
@@ -184,6 +188,7 @@ def _make_desc(*, ndim, nx, ny, nz, shape, radius, weights, T, tb_depth, n_chunk
     d.adjoint = 1 if adjoint else 0
     d.method = METHODS[method]
     d.rounding = ROUNDING[rounding]
+    d.copy_engine = COPY_ENGINES[copy_engine]
     return d, w
 
 
@@ -208,7 +213,8 @@ def suggest(machine=None, **plan_kwargs):
     n_slots) with the combination of least predicted time that fits the
     budget.  Returns (plan keyword arguments, predicted ms)."""
     kw = dict(nz=1, shape="star", radius=1, tb_depth=0, n_chunks=0, k_on=0, n_slots=0,
-              storage="f32", bc=(0, 0, 0), adjoint=False, method="so2dr", rounding="every_step")
+              storage="f32", bc=(0, 0, 0), adjoint=False, method="so2dr", rounding="every_step",
+              copy_engine="auto")
     kw.update(plan_kwargs)
     d, keep = _make_desc(**kw)
     out = _lib.Desc()

@@ -81,6 +81,29 @@ def test_adjoint_checkpoint_interval_invariance():
         assert _gw_err(other[2], res[0][2]) <= 1e-10
 
 
+def test_adjoint_copy_engines_bitwise():
+    """The gradient with host copies by copy kernels equals the one with DMA
+    copies bit for bit (loss, dL/du0, dL/dw)."""
+    rng = np.random.default_rng(73)
+    offs = oracle.stencil_offsets(3, "star", 1)
+    w = rng.uniform(0.05, 0.2, len(offs))
+    nx, ny, nz = 40, 24, 30
+    kw = dict(ndim=3, nx=nx, ny=ny, nz=nz, shape="star", radius=1, weights=list(w), T=10,
+              tb_depth=4, n_chunks=3, budget=1 << 30)
+    u0 = to_storage(rng.random((nz, ny, nx)), "f32")
+    y = to_storage(rng.random((nz, ny, nx)), "f32")
+    res = []
+    for engine in ("dma", "kernel"):
+        p = Plan(adjoint=True, copy_engine=engine, **kw).bind()
+        assert p.info()["copy_engine"] == {"dma": 1, "kernel": 2}[engine]
+        loss, gu, gw, _ = p.adjoint(pinned_copy(u0), pinned_copy(y), 4)
+        res.append((loss, gu.clone(), gw))
+        p.close()
+    assert res[0][0] == res[1][0]
+    assert torch.equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][2], res[1][2])
+
+
 def _gpu_loss(kw, u0, y):
     p = Plan(**kw).bind()
     h = pinned_copy(u0)

@@ -10,7 +10,8 @@ import pytest
 import torch
 
 import oracle
-from helpers import (STENCIL_CASES, fp32_weights, gpu_run, np_shape, rel_l2, to_storage)
+from helpers import (STENCIL_CASES, fp32_weights, gpu_run, np_shape, pinned_copy, rel_l2,
+                     to_storage)
 
 pytestmark = pytest.mark.gpu
 
@@ -200,6 +201,46 @@ def test_library_pinned_host_fields():
         del h, out
         gc.collect()
     assert pinned_empty((0, 5), torch.float32).numel() == 0
+
+
+@pytest.mark.parametrize("ndim,shape,r,storage,nx", [(3, "star", 1, "f32", 264), (3, "box", 1, "bf16", 264),
+                                                  (2, "star", 1, "f16", 1100), (3, "star", 1, "f32", 37)])
+def test_copy_engines_bitwise(ndim, shape, r, storage, nx):
+    """Host copies by copy kernels through the host mapping and by the DMA
+    engines give the same bits, in place and out of place, for PyTorch's
+    pinned tensors and for so2dr_host_alloc memory.  nx = 37 makes rows of
+    148 bytes, so some copies are not 16-byte aligned and take the DMA path
+    inside a copy-kernel plan."""
+    from paper_2309_08864_amd import Plan, pinned_empty
+    rng = np.random.default_rng(71)
+    offs = _offsets(ndim, shape, r)
+    w = _weights(offs, rng)
+    _, ny, nz = _dims(ndim)
+    kw = _kwargs(ndim, shape, r, w, T=9, K=4, d=3, k_on=2, storage=storage)
+    kw["nx"] = nx
+    u0 = to_storage(rng.random(np_shape(ndim, nx, ny, nz)), storage)
+    outs = []
+    for engine in ("dma", "kernel"):
+        p = Plan(copy_engine=engine, **kw)
+        assert p.info()["copy_engine"] == {"dma": 1, "kernel": 2}[engine]
+        p.bind()
+        for alloc in ("torch", "library"):
+            if alloc == "torch":
+                h = pinned_copy(u0)
+                o = torch.empty(u0.shape, dtype=u0.dtype, pin_memory=True)
+            else:
+                h = pinned_empty(u0.shape, u0.dtype)
+                h.copy_(u0)
+                o = pinned_empty(u0.shape, u0.dtype)
+            p.run_steps(h, o, 7)
+            outs.append(o.clone())
+            p.run(h)
+            outs.append(h.clone())
+        p.close()
+    for k in range(2, len(outs)):
+        assert torch.equal(outs[k], outs[k % 2]), k
+    ref = oracle.sweep(u0.double().numpy(), offs, fp32_weights(w), 9)
+    assert rel_l2(outs[1].double().numpy(), ref) <= (1e-5 if storage == "f32" else 2e-2)
 
 
 def test_edge_cases():

@@ -217,6 +217,33 @@ def test_error_paths():
         p.run(torch.zeros(64 * 16 * 16))
 
 
+def test_copy_engine_choice():
+    """Automatic copy engine: copy kernels below 512 MiB per chunk copy, DMA
+    from there on; an explicit choice is kept; unknown values are refused."""
+    import ctypes
+    from paper_2309_08864_amd import _lib
+    from paper_2309_08864_amd.plan import _make_desc
+    offs, w = _w(3, "star", 1)
+    base = dict(ndim=3, nx=2048, ny=1024, nz=1024, shape="star", radius=1, weights=w, T=64,
+                tb_depth=8, budget=4 << 30)
+    assert Plan(n_chunks=16, **base).info()["copy_engine"] == 1      # 512 MiB copies: DMA
+    assert Plan(n_chunks=32, **base).info()["copy_engine"] == 2      # 256 MiB: kernels
+    assert Plan(n_chunks=32, copy_engine="dma", **base).info()["copy_engine"] == 1
+    assert Plan(n_chunks=16, copy_engine="kernel", **base).info()["copy_engine"] == 2
+    kw = dict(base, nz=1024, tb_depth=8, n_chunks=16, k_on=0, n_slots=0, storage="f32",
+              bc=(0, 0, 0), adjoint=False, method="so2dr", rounding="every_step")
+    d, keep = _make_desc(**kw)
+    d.copy_engine = 7
+    h = ctypes.c_void_p()
+    assert _lib.lib().so2dr_plan_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    # the cost model prices copy kernels at their own both-directions rate
+    pk = Plan(n_chunks=16, copy_engine="kernel", **base)
+    pd = Plan(n_chunks=16, copy_engine="dma", **base)
+    m = pd.machine()
+    assert m["kcopy_gbps"] < m["duplex_gbps"]
+    assert pk.predict() > pd.predict() * 1.05
+
+
 def test_host_alloc_argument_paths():
     """so2dr_host_alloc / so2dr_host_free paths that make no HIP call."""
     import ctypes

@@ -53,7 +53,7 @@ CONFIGS = {
         dtypes=("f32", "bf16", "f16"),
         notes="3D 13-point radius-2 star; BF16/FP16 storage vs FP32"),
     "c5_adjoint": Workload(
-        "c5_adjoint", 3, 1024, 1024, 1024, "star", 1, T=128, tb_depth=8, n_chunks=16,
+        "c5_adjoint", 3, 1024, 1024, 1024, "star", 1, T=128, tb_depth=8, n_chunks=0,
         budget=2 * GiB, seed=5, init="uniform", weights="centre_arm:0.4:0.1",
         notes="adjoint of the 7-point sweep, checkpoints every 16 steps",
         extra={"ckpt_every": 16, "target_seed": 50}),
