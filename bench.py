@@ -104,9 +104,9 @@ HOST_ALLOC = "so2dr"
 
 
 def host_empty(shape, dtype):
-    """Page-locked host tensor: from the library's allocator (the runtime's
-    own, whose copies run on the DMA engines) or, with --host-alloc torch,
-    PyTorch's pinned allocator."""
+    """Page-locked host tensor: from the library's allocator (the HIP
+    runtime's own, one mapped allocation per field) or, with --host-alloc
+    torch, PyTorch's pinned allocator."""
     import torch
     if HOST_ALLOC == "torch":
         return torch.empty(shape, dtype=dtype, pin_memory=True)

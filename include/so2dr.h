@@ -242,10 +242,8 @@ int so2dr_adjoint_run(struct so2dr_plan *plan, const void *host_u0, const void *
  * memory management; not in the paper).  *ptr receives `bytes` bytes from
  * the HIP runtime's own page-locked allocator (default flags), 4096-byte
  * aligned and owned by the caller until so2dr_host_free; bytes == 0 gives
- * *ptr = NULL.  The runtime moves such memory to and from HBM on its DMA
- * engines (SO2DR_COPY_DMA).  Page-locked memory from other allocators may
- * instead be copied by the runtime's own copy kernels (measured on MI355X for
- * PyTorch's pinned tensors, HBM -> host direction).
+ * *ptr = NULL.  The allocation is mapped into the device, as copy kernels
+ * (SO2DR_COPY_KERNEL) need, and its size is exactly `bytes`.
  * Errors: E_INVALID (null ptr), E_HIP (allocation failed; *ptr = NULL). */
 int so2dr_host_alloc(size_t bytes, void **ptr);
 

@@ -183,9 +183,9 @@ class _HostBlock:
 
 def pinned_empty(shape, dtype):
     """Uninitialised CPU tensor of `shape` and torch `dtype` in page-locked
-    memory from the HIP runtime's own allocator (so2dr_host_alloc): its
-    copies to and from HBM run on the DMA engines, leaving the compute units
-    to the stencil kernels."""
+    memory from the HIP runtime's own allocator (so2dr_host_alloc): one
+    mapped allocation of exactly the tensor's size, released with the last
+    tensor that views it."""
     import torch
     shape = tuple(int(n) for n in (shape if isinstance(shape, (tuple, list)) else (shape,)))
     n = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
