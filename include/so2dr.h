@@ -87,8 +87,9 @@ typedef enum { SO2DR_ROUND_EVERY_STEP = 0, SO2DR_ROUND_AT_STORE = 1 } so2dr_roun
  *     host array must be one page-locked allocation mapped into the device,
  *     else the run fails with E_NOT_PINNED.
  *   SO2DR_COPY_AUTO: copy kernels when the plan's largest chunk copy is
- *     below a measured threshold (512 MiB), the plan is not an adjoint plan
- *     and both host arrays are mapped; else DMA. */
+ *     below 512 MiB, a run of T steps queues more than 256 host copies
+ *     (2 x chunks x rounds), the plan is not an adjoint plan and both host
+ *     arrays are mapped; else DMA (thresholds measured on MI355X). */
 typedef enum { SO2DR_COPY_AUTO = 0, SO2DR_COPY_DMA = 1, SO2DR_COPY_KERNEL = 2 } so2dr_copy_engine;
 
 /* Problem and run-time configuration: the variables of the paper's Table I

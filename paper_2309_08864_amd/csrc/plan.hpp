@@ -82,8 +82,10 @@ int stencil_id(int ndim, int shape, int r);
 int expected_points(int ndim, int shape, int r);
 
 // Automatic copy engine: copy kernels when the largest chunk copy is below
-// this many bytes, the DMA engines otherwise.
+// kKernelCopyBelow bytes and a run queues more than kKernelCopyQueued host
+// copies at once; the DMA engines otherwise.
 constexpr size_t kKernelCopyBelow = (size_t)512 << 20;
+constexpr int64_t kKernelCopyQueued = 256;
 // Workgroups of one host-copy kernel (about the link's rate per direction).
 constexpr int kHostCopyWgs = 64;
 

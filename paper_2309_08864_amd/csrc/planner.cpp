@@ -446,7 +446,9 @@ int make_plan(const so2dr_desc &D, Plan *P) {
   // Copy engine.  Measured on MI355X with everything enqueued at once, DMA
   // copies ran at the link's 97 GB/s only while each copy was large; with
   // smaller copies the rate became erratic (a 64 MiB pattern: 28-82 GB/s
-  // over repeats) while copy kernels held 84-86 GB/s at any size.  Adjoint
+  // over repeats) while copy kernels held 84-86 GB/s at any size.  Few queued
+  // copies stay fast on DMA (the 27-point workload at 32 chunks and two
+  // rounds: 190 GCell/s), so the count queued by one run counts too.  Adjoint
   // plans keep DMA: their reverse sweep waits for each round and its compute
   // kernels compete with copy kernels (the 1024^3 gradient: 4.9 s with DMA,
   // 7.2 s with copy kernels).
@@ -456,8 +458,11 @@ int make_plan(const so2dr_desc &D, Plan *P) {
   } else {
     int64_t own = 0;
     for (int i = 0; i < P->d; ++i) own = std::max<int64_t>(own, P->bnd[i + 1] - P->bnd[i]);
-    P->copy_engine = !P->adjoint && (size_t)own * P->plane_bytes() < kKernelCopyBelow ? SO2DR_COPY_KERNEL
-                                                                                       : SO2DR_COPY_DMA;
+    const int64_t rounds = P->K > 0 ? (P->T + P->K - 1) / P->K : 1;
+    const int64_t queued = 2 * (int64_t)P->d * rounds;
+    P->copy_engine = !P->adjoint && (size_t)own * P->plane_bytes() < kKernelCopyBelow && queued > kKernelCopyQueued
+                         ? SO2DR_COPY_KERNEL
+                         : SO2DR_COPY_DMA;
   }
   return SO2DR_OK;
 }

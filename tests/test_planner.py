@@ -218,9 +218,9 @@ def test_error_paths():
 
 
 def test_copy_engine_choice():
-    """Automatic copy engine: copy kernels below 512 MiB per chunk copy, DMA
-    from there on and for adjoint plans; an explicit choice is kept; unknown
-    values are refused."""
+    """Automatic copy engine: copy kernels below 512 MiB per chunk copy when a
+    run queues more than 256 copies, DMA otherwise and for adjoint plans; an
+    explicit choice is kept; unknown values are refused."""
     import ctypes
     from paper_2309_08864_amd import _lib
     from paper_2309_08864_amd.plan import _make_desc
@@ -232,6 +232,7 @@ def test_copy_engine_choice():
     assert Plan(n_chunks=32, copy_engine="dma", **base).info()["copy_engine"] == 1
     assert Plan(n_chunks=16, copy_engine="kernel", **base).info()["copy_engine"] == 2
     assert Plan(n_chunks=32, adjoint=True, **dict(base, budget=8 << 30)).info()["copy_engine"] == 1
+    assert Plan(n_chunks=32, **dict(base, T=32, tb_depth=16)).info()["copy_engine"] == 1  # 128 copies
     kw = dict(base, nz=1024, tb_depth=8, n_chunks=16, k_on=0, n_slots=0, storage="f32",
               bc=(0, 0, 0), adjoint=False, method="so2dr", rounding="every_step")
     d, keep = _make_desc(**kw)
