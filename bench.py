@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--host-alloc", default="so2dr", choices=["so2dr", "torch"],
                     help="allocator of the pinned host fields")
-    ap.add_argument("--copy-engine", default="auto", choices=["auto", "dma", "kernel"],
+    ap.add_argument("--copy-engine", default="auto", choices=["auto", "dma", "kernel", "kernel_out"],
                     help="what moves chunks between host and HBM")
     ap.add_argument("--cpu-sample-planes", type=int, default=0)
     ap.add_argument("--compare-storage", default=None,
@@ -213,7 +213,7 @@ def bench_adjoint(args, wl, w):
                         f"budget {wl.budget / 2**30:g} GiB",
             "cells": wl.cells, "T": wl.T, "workspace_bytes": info["workspace_bytes"],
             "host_checkpoint_fields": len(ckpt), "host_alloc": args.host_alloc,
-            "copy_engine": {1: "dma", 2: "kernel"}[info["copy_engine"]]},
+            "copy_engine": {1: "dma", 2: "kernel", 3: "kernel_out"}[info["copy_engine"]]},
         "forward_GCells": round(wl.cells * wl.T / t_fwd / 1e9, 3),
         "gradient_over_forward_time": round(elapsed / args.steps / t_fwd, 3),
         "link": {"achieved_GBps": round(link / elapsed / 1e9, 2), "peak_GBps": LINK_PEAK_GBPS},
@@ -331,7 +331,7 @@ def main():
             "method": args.method, "lean": info["lean"], "rounding": args.rounding,
             "planned_by": "cost model" if args.auto else "given",
             "host_alloc": args.host_alloc,
-            "copy_engine": {1: "dma", 2: "kernel"}[info["copy_engine"]],
+            "copy_engine": {1: "dma", 2: "kernel", 3: "kernel_out"}[info["copy_engine"]],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -86,11 +86,19 @@ typedef enum { SO2DR_ROUND_EVERY_STEP = 0, SO2DR_ROUND_AT_STORE = 1 } so2dr_roun
  *     85 GB/s both directions together, independent of the copy size); the
  *     host array must be one page-locked allocation mapped into the device,
  *     else the run fails with E_NOT_PINNED.
- *   SO2DR_COPY_AUTO: copy kernels when the plan's largest chunk copy is
+ *   SO2DR_COPY_KERNEL_OUT: hipMemcpyAsync host -> HBM, copy kernels
+ *     HBM -> host (same requirement on the host arrays).
+ *   SO2DR_COPY_AUTO: KERNEL_OUT when the plan's largest chunk copy is
  *     below 512 MiB, a run of T steps queues more than 256 host copies
  *     (2 x chunks x rounds), the plan is not an adjoint plan and both host
- *     arrays are mapped; else DMA (thresholds measured on MI355X). */
-typedef enum { SO2DR_COPY_AUTO = 0, SO2DR_COPY_DMA = 1, SO2DR_COPY_KERNEL = 2 } so2dr_copy_engine;
+ *     arrays are mapped; else DMA (thresholds measured on MI355X; 7-point
+ *     2048x1024x1024 at 32 chunks: 88 GB/s KERNEL_OUT, 77 KERNEL, 42 DMA). */
+typedef enum {
+  SO2DR_COPY_AUTO = 0,
+  SO2DR_COPY_DMA = 1,
+  SO2DR_COPY_KERNEL = 2,
+  SO2DR_COPY_KERNEL_OUT = 3
+} so2dr_copy_engine;
 
 /* Problem and run-time configuration: the variables of the paper's Table I
  * (dim, sz, r, d, S_tot, S_TB, N_strm, C_dmem) plus the stencil itself. */
@@ -134,7 +142,8 @@ typedef struct {
   double redundant_fraction;  /* recomputed / useful cell updates */
   int64_t n_ops;              /* entries in the operation schedule */
   int rounding;               /* the so2dr_rounding value in effect: EVERY_STEP unless 16-bit storage */
-  int copy_engine;            /* SO2DR_COPY_DMA or _KERNEL: what runs use when the host arrays allow */
+  int copy_engine;            /* SO2DR_COPY_DMA, _KERNEL or _KERNEL_OUT: what runs use when the host
+                                 arrays allow */
 } so2dr_plan_info;
 
 /* One entry of the schedule the executor runs (Algorithm 1, unrolled).
@@ -262,7 +271,8 @@ typedef struct {
   double launch_us;            /* fixed cost of one kernel launch */
   double gupd[8];              /* output cells x levels per second of a fused
                                   launch of 1..8 levels; 0 = not available */
-  double kcopy_gbps;           /* both directions at once with copy kernels */
+  double kcopy_gbps;           /* both directions at once with copy kernels (COPY_KERNEL) */
+  double kcopy_out_gbps;       /* both directions at once, DMA in and copy kernels out */
 } so2dr_machine;
 
 /* Fill *m with the library's built-in figures for this plan's stencil and

@@ -15,7 +15,7 @@ DTYPES = {"f32": 0, "f64": 1, "bf16": 2, "f16": 3}
 SHAPES = {"star": 0, "box": 1}
 METHODS = {"so2dr": 0, "resreu": 1}
 ROUNDING = {"every_step": 0, "at_store": 1}
-COPY_ENGINES = {"auto": 0, "dma": 1, "kernel": 2}
+COPY_ENGINES = {"auto": 0, "dma": 1, "kernel": 2, "kernel_out": 3}
 OP_KINDS = {0: "H2D", 1: "RS_READ", 2: "RS_WRITE", 3: "KERNEL", 4: "D2H"}
 
 # Symbols the header declares; the CPU test checks each is exported.
@@ -41,7 +41,7 @@ class Machine(ctypes.Structure):
     _fields_ = [("h2d_gbps", ctypes.c_double), ("d2h_gbps", ctypes.c_double),
                 ("duplex_gbps", ctypes.c_double), ("d2d_gbps", ctypes.c_double),
                 ("launch_us", ctypes.c_double), ("gupd", ctypes.c_double * 8),
-                ("kcopy_gbps", ctypes.c_double)]
+                ("kcopy_gbps", ctypes.c_double), ("kcopy_out_gbps", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -103,7 +103,8 @@ static LaunchParams base_launch(const Plan &P, const double *w) {
 
 struct AdjCtx {
   hipStream_t s_in, s_out, s_comp;
-  bool kcopy = false;  // host copies by copy kernels through the host mappings
+  bool kcopy = false;  // HBM -> host copies by copy kernels through the host mappings
+  bool kcopy_in = false;  // host -> HBM copies too
   size_t field = 0;
   double *partials, *acc_w, *acc_loss;
   std::vector<double> wT;  // reflected weights
@@ -118,14 +119,15 @@ static int loss_pass(Plan &P, AdjCtx &C, void *lam_host, const void *y_host, so2
   ARC(ensure(P.ev_comp, P.d));
   ARC(ensure(P.ev_d2h, P.d));
   char *d_lam = C.kcopy ? mapped_host(lam_host, C.field) : nullptr;
-  char *d_y = C.kcopy ? mapped_host(y_host, C.field) : nullptr;
+  char *d_lam_in = C.kcopy_in ? d_lam : nullptr;
+  char *d_y = C.kcopy_in ? mapped_host(y_host, C.field) : nullptr;
   for (int i = 0; i < P.d; ++i) {
     const int slot = i % P.n_slots;
     const int64_t z0 = P.bnd[i], z1 = P.bnd[i + 1];
     const size_t n = (size_t)(z1 - z0) * pb;
     char *ub = P.slot_buf(slot, 0), *yb = P.slot_buf(slot, 1);
     if (i >= P.n_slots) AHIP(hipStreamWaitEvent(C.s_in, P.ev_d2h[i - P.n_slots], 0));
-    ARC(copy_to_device(ub, static_cast<char *>(lam_host) + (size_t)z0 * pb, n, lam_host, d_lam, C.s_in));
+    ARC(copy_to_device(ub, static_cast<char *>(lam_host) + (size_t)z0 * pb, n, lam_host, d_lam_in, C.s_in));
     ARC(copy_to_device(yb, static_cast<const char *>(y_host) + (size_t)z0 * pb, n, y_host, d_y, C.s_in));
     AHIP(hipEventRecord(P.ev_h2d[i], C.s_in));
     AHIP(hipStreamWaitEvent(C.s_comp, P.ev_h2d[i], 0));
@@ -160,8 +162,9 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
   ARC(ensure(P.ev_d2h, P.d));
   ARC(ensure(P.ev_rs, P.d));
   std::string msg;
-  char *d_u = C.kcopy ? mapped_host(u_host, C.field) : nullptr;
+  char *d_u = C.kcopy_in ? mapped_host(u_host, C.field) : nullptr;
   char *d_lam = C.kcopy ? mapped_host(lam_host, C.field) : nullptr;
+  char *d_lam_in = C.kcopy_in ? d_lam : nullptr;
   LaunchParams fwd = base_launch(P, P.weights.data());
   LaunchParams adj = base_launch(P, C.wT.data());
   for (int i = 0; i < P.d; ++i) {
@@ -175,7 +178,7 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
     const size_t own = (size_t)(b1 - b0) * pb;
     ARC(copy_to_device(at(U0, b0), static_cast<const char *>(u_host) + (size_t)b0 * pb, own, u_host, d_u,
                        C.s_in));
-    ARC(copy_to_device(at(LA, b0), static_cast<char *>(lam_host) + (size_t)b0 * pb, own, lam_host, d_lam,
+    ARC(copy_to_device(at(LA, b0), static_cast<char *>(lam_host) + (size_t)b0 * pb, own, lam_host, d_lam_in,
                        C.s_in));
     AHIP(hipEventRecord(P.ev_h2d[i], C.s_in));
     S->bytes_h2d += 2 * own;
@@ -312,7 +315,8 @@ int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, doub
   const auto t0 = std::chrono::steady_clock::now();
   AdjCtx C;
   C.field = field;
-  C.kcopy = P.copy_engine == SO2DR_COPY_KERNEL;
+  C.kcopy = P.copy_engine == SO2DR_COPY_KERNEL || P.copy_engine == SO2DR_COPY_KERNEL_OUT;
+  C.kcopy_in = P.copy_engine == SO2DR_COPY_KERNEL;
   if (C.kcopy) {
     bool all = mapped_host(u0, field) && mapped_host(target, field) && mapped_host(grad_u0, field);
     for (int j = 0; j < need; ++j) all = all && mapped_host(ckpt[j], field);
@@ -321,7 +325,7 @@ int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, doub
         set_error("copy kernels need each host array inside one page-locked allocation mapped into the device");
         return SO2DR_E_NOT_PINNED;
       }
-      C.kcopy = false;
+      C.kcopy = C.kcopy_in = false;
     }
   }
   const int ns = (int)P.streams.size();

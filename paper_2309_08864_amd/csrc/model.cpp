@@ -51,7 +51,8 @@ void default_machine(const Plan &P, so2dr_machine *m) {
   m->duplex_gbps = 97.3;
   m->d2d_gbps = 2000.0;
   m->launch_us = 8.0;
-  m->kcopy_gbps = 77.0;  // copy kernels of 64 workgroups, both directions at once, beside stencil kernels
+  m->kcopy_gbps = 77.0;      // copy kernels of 64 workgroups both ways, beside stencil kernels
+  m->kcopy_out_gbps = 88.0;  // DMA in, copy kernels out
   const int md = max_depth(P.dtype, P.stencil);
   for (int k = 1; k <= 8; ++k) {
     double g = (P.stencil >= 0 && P.stencil < 8) ? kRateF32[P.stencil][k - 1] : 0.0;
@@ -70,7 +71,9 @@ double simulate(const Plan &P, const so2dr_machine &m, int steps) {
   const size_t nseq = (size_t)std::max(nt, 1) * P.d;
   // with two or more slots both copy directions run together most of the time
   const bool duplex = P.n_slots >= 2;
-  const double both = P.copy_engine == SO2DR_COPY_KERNEL && m.kcopy_gbps > 0 ? m.kcopy_gbps : m.duplex_gbps;
+  double both = m.duplex_gbps;
+  if (P.copy_engine == SO2DR_COPY_KERNEL && m.kcopy_gbps > 0) both = m.kcopy_gbps;
+  if (P.copy_engine == SO2DR_COPY_KERNEL_OUT && m.kcopy_out_gbps > 0) both = m.kcopy_out_gbps;
   Sim S;
   S.bw_in = 1e9 * (duplex ? std::min(m.h2d_gbps, 0.5 * both) : m.h2d_gbps);
   S.bw_out = 1e9 * (duplex ? std::min(m.d2h_gbps, 0.5 * both) : m.d2h_gbps);

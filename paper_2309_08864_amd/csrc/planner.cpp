@@ -384,7 +384,7 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     return SO2DR_E_INVALID;
   }
   P->ras = D.rounding == SO2DR_ROUND_AT_STORE && (P->dtype == SO2DR_BF16 || P->dtype == SO2DR_F16);
-  if (D.copy_engine != SO2DR_COPY_AUTO && D.copy_engine != SO2DR_COPY_DMA && D.copy_engine != SO2DR_COPY_KERNEL) {
+  if (D.copy_engine < SO2DR_COPY_AUTO || D.copy_engine > SO2DR_COPY_KERNEL_OUT) {
     set_error("unknown copy engine");
     return SO2DR_E_INVALID;
   }
@@ -446,7 +446,9 @@ int make_plan(const so2dr_desc &D, Plan *P) {
   // Copy engine.  Measured on MI355X with everything enqueued at once, DMA
   // copies ran at the link's 97 GB/s only while each copy was large; with
   // smaller copies the rate became erratic (a 64 MiB pattern: 28-82 GB/s
-  // over repeats) while copy kernels held 84-86 GB/s at any size.  Few queued
+  // over repeats) while copy kernels held 84-86 GB/s at any size; DMA in with
+  // copy kernels out did best in the executor (the 7-point workload at 32
+  // chunks: 88 GB/s, against 77 with kernels both ways).  Few queued
   // copies stay fast on DMA (the 27-point workload at 32 chunks and two
   // rounds: 190 GCell/s), so the count queued by one run counts too.  Adjoint
   // plans keep DMA: their reverse sweep waits for each round and its compute
@@ -461,7 +463,7 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     const int64_t rounds = P->K > 0 ? (P->T + P->K - 1) / P->K : 1;
     const int64_t queued = 2 * (int64_t)P->d * rounds;
     P->copy_engine = !P->adjoint && (size_t)own * P->plane_bytes() < kKernelCopyBelow && queued > kKernelCopyQueued
-                         ? SO2DR_COPY_KERNEL
+                         ? SO2DR_COPY_KERNEL_OUT
                          : SO2DR_COPY_DMA;
   }
   return SO2DR_OK;

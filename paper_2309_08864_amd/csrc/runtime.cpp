@@ -187,7 +187,8 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
   if (rc) return rc;
   // device mappings for copy kernels (null: hipMemcpyAsync)
   char *dev_in = nullptr, *dev_out = nullptr;
-  if (P.copy_engine == SO2DR_COPY_KERNEL) {
+  bool k_in = P.copy_engine == SO2DR_COPY_KERNEL;
+  if (k_in || P.copy_engine == SO2DR_COPY_KERNEL_OUT) {
     dev_in = mapped_host(host_in, field);
     dev_out = host_out == host_in ? dev_in : mapped_host(host_out, field);
     if (!dev_in || !dev_out) {
@@ -196,6 +197,7 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
         return SO2DR_E_NOT_PINNED;
       }
       dev_in = dev_out = nullptr;
+      k_in = false;
     }
   }
   so2dr_stats S;
@@ -276,7 +278,7 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
     switch (op.kind) {
       case SO2DR_OP_H2D: {
         const char *base = op.round == 0 ? hin : hout;
-        char *dev = op.round == 0 ? dev_in : dev_out;
+        char *dev = !k_in ? nullptr : op.round == 0 ? dev_in : dev_out;
         char *dst = P.slot_buf(op.slot, op.buf_out) + (size_t)(op.z0 - op.buf_z0) * pb;
         rc = copy_to_device(dst, base + (size_t)op.z0 * pb, (size_t)(op.z1 - op.z0) * pb, base, dev, s);
         if (rc) return rc;

@@ -93,15 +93,16 @@ def test_adjoint_copy_engines_bitwise():
     u0 = to_storage(rng.random((nz, ny, nx)), "f32")
     y = to_storage(rng.random((nz, ny, nx)), "f32")
     res = []
-    for engine in ("dma", "kernel"):
+    for engine in ("dma", "kernel", "kernel_out"):
         p = Plan(adjoint=True, copy_engine=engine, **kw).bind()
-        assert p.info()["copy_engine"] == {"dma": 1, "kernel": 2}[engine]
+        assert p.info()["copy_engine"] == {"dma": 1, "kernel": 2, "kernel_out": 3}[engine]
         loss, gu, gw, _ = p.adjoint(pinned_copy(u0), pinned_copy(y), 4)
         res.append((loss, gu.clone(), gw))
         p.close()
-    assert res[0][0] == res[1][0]
-    assert torch.equal(res[0][1], res[1][1])
-    assert np.array_equal(res[0][2], res[1][2])
+    for r in res[1:]:
+        assert res[0][0] == r[0]
+        assert torch.equal(res[0][1], r[1])
+        assert np.array_equal(res[0][2], r[2])
 
 
 def _gpu_loss(kw, u0, y):

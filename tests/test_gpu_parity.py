@@ -220,9 +220,9 @@ def test_copy_engines_bitwise(ndim, shape, r, storage, nx):
     kw["nx"] = nx
     u0 = to_storage(rng.random(np_shape(ndim, nx, ny, nz)), storage)
     outs = []
-    for engine in ("dma", "kernel"):
+    for engine in ("dma", "kernel", "kernel_out"):
         p = Plan(copy_engine=engine, **kw)
-        assert p.info()["copy_engine"] == {"dma": 1, "kernel": 2}[engine]
+        assert p.info()["copy_engine"] == {"dma": 1, "kernel": 2, "kernel_out": 3}[engine]
         p.bind()
         for alloc in ("torch", "library"):
             if alloc == "torch":

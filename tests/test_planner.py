@@ -218,9 +218,9 @@ def test_error_paths():
 
 
 def test_copy_engine_choice():
-    """Automatic copy engine: copy kernels below 512 MiB per chunk copy when a
-    run queues more than 256 copies, DMA otherwise and for adjoint plans; an
-    explicit choice is kept; unknown values are refused."""
+    """Automatic copy engine: copy kernels for the copy-out below 512 MiB per
+    chunk copy when a run queues more than 256 copies, DMA otherwise and for
+    adjoint plans; an explicit choice is kept; unknown values are refused."""
     import ctypes
     from paper_2309_08864_amd import _lib
     from paper_2309_08864_amd.plan import _make_desc
@@ -228,7 +228,7 @@ def test_copy_engine_choice():
     base = dict(ndim=3, nx=2048, ny=1024, nz=1024, shape="star", radius=1, weights=w, T=64,
                 tb_depth=8, budget=4 << 30)
     assert Plan(n_chunks=16, **base).info()["copy_engine"] == 1      # 512 MiB copies: DMA
-    assert Plan(n_chunks=32, **base).info()["copy_engine"] == 2      # 256 MiB: kernels
+    assert Plan(n_chunks=32, **base).info()["copy_engine"] == 3      # 256 MiB: kernels out
     assert Plan(n_chunks=32, copy_engine="dma", **base).info()["copy_engine"] == 1
     assert Plan(n_chunks=16, copy_engine="kernel", **base).info()["copy_engine"] == 2
     assert Plan(n_chunks=32, adjoint=True, **dict(base, budget=8 << 30)).info()["copy_engine"] == 1
@@ -245,6 +245,9 @@ def test_copy_engine_choice():
     m = pd.machine()
     assert m["kcopy_gbps"] < m["duplex_gbps"]
     assert pk.predict() > pd.predict() * 1.05
+    po = Plan(n_chunks=16, copy_engine="kernel_out", **base)
+    assert m["kcopy_gbps"] < m["kcopy_out_gbps"] < m["duplex_gbps"]
+    assert pk.predict() > po.predict() > pd.predict()
 
 
 def test_host_alloc_argument_paths():
