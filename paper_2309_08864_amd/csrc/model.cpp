@@ -149,12 +149,13 @@ double predict_seconds(const Plan &P, const so2dr_machine &m, int steps) {
 
 namespace {
 
-// Chunk counts searched.  Measured on MI355X, some runs with 32 or more chunks
-// per round lost up to half their copy-out rate in this executor (copies
-// timed by events at 20-25 GB/s instead of 49), which the model does not
-// capture; so the search stops at 32 chunks and takes a candidate with more
-// chunks, more fused levels or a deeper round only when it is predicted more
-// than 1 % faster (candidates are visited in increasing order).
+// Chunk counts searched.  Measured on MI355X, many small host copies run
+// slower than the model's link figures: DMA copies collapse when hundreds are
+// queued (the reason for the copy-kernel modes), and even DMA in with copy
+// kernels out fell from 88 to 69 GB/s at 64 chunks of the 7-point workload.
+// So the search stops at 32 chunks and takes a candidate with more chunks,
+// more fused levels or a deeper round only when it is predicted more than
+// 1 % faster (candidates are visited in increasing order).
 constexpr int64_t kMaxSearchChunks = 32;
 constexpr double kMinGain = 0.01;
 
