@@ -243,6 +243,26 @@ def test_copy_engines_bitwise(ndim, shape, r, storage, nx):
     assert rel_l2(outs[1].double().numpy(), ref) <= (1e-5 if storage == "f32" else 2e-2)
 
 
+def test_automatic_copy_engine_many_small_copies():
+    """A plan that queues more than 256 small host copies takes DMA in with
+    copy kernels out by itself; its bits equal the DMA plan's and it stays
+    within the FP32 tolerance of the oracle."""
+    from paper_2309_08864_amd import Plan
+    rng = np.random.default_rng(79)
+    offs = _offsets(3, "star", 1)
+    w = _weights(offs, rng)
+    nx, ny, nz = 264, 37, 200
+    kw = dict(ndim=3, nx=nx, ny=ny, nz=nz, shape="star", radius=1, weights=list(w), T=16,
+              tb_depth=2, n_chunks=20, budget=1 << 30)
+    u0 = to_storage(rng.random((nz, ny, nx)), "f32")
+    assert Plan(**kw).info()["copy_engine"] == 3          # 2 x 20 chunks x 8 rounds = 320 copies
+    auto, _, _ = gpu_run(kw, u0)
+    dma, _, _ = gpu_run(dict(kw, copy_engine="dma"), u0)
+    assert torch.equal(auto, dma)
+    ref = oracle.sweep(u0.double().numpy(), offs, fp32_weights(w), 16)
+    assert rel_l2(auto.double().numpy(), ref) <= 1e-5
+
+
 def test_edge_cases():
     """Tiny grids (smaller than one tile), a single plane per chunk of the
     last chunk, T = 1, nx = 1 and chunks of exactly 2 r K planes."""
