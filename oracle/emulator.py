@@ -111,3 +111,67 @@ def sweep_bits(u0, offsets, weights, T, storage="f32", periodic=(0, 0, 0), round
             acc = fma32(wk, _shifted(u, o, periodic), acc)
         u = rnd(acc) if round_after is None or t in round_after else acc
     return u[0] if two_d else u
+
+
+# ---------------------------------------------------------------- C model
+# emulator_bits.c computes the same arithmetic with the C library's correctly
+# rounded fmaf, fast enough for grids of tens of millions of cells; it is
+# checked against sweep_bits above in the tests.
+
+_STORAGE_CODE = {"f32": 0, "bf16": 2, "f16": 3}
+
+
+def _c_args(offsets, weights, periodic, T, round_after):
+    import ctypes
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+    w32 = np.ascontiguousarray(np.asarray(weights, np.float64).astype(np.float32).reshape(-1))
+    per = np.ascontiguousarray(np.asarray(periodic, dtype=np.int32).reshape(3))
+    flags = None
+    if round_after is not None:
+        flags = np.zeros(T + 1, np.uint8)
+        for t in round_after:
+            if 1 <= t <= T:
+                flags[t] = 1
+    ptr = (lambda a: a.ctypes.data_as(ctypes.c_void_p) if a is not None else None)
+    return off, w32, per, flags, ptr
+
+
+def sweep_bits_c(u0, offsets, weights, T, storage="f32", periodic=(0, 0, 0), round_after=None):
+    """sweep_bits computed by the C model (same arguments and result)."""
+    from .oracle import _lib
+    two_d = np.asarray(u0).ndim == 2
+    u = np.ascontiguousarray(np.asarray(u0, np.float32))
+    u3 = u[None] if two_d else u
+    nz, ny, nx = u3.shape
+    off, w32, per, flags, ptr = _c_args(offsets, weights, periodic, T, round_after)
+    out = np.empty_like(u3)
+    rc = _lib().emu_sweep(nx, ny, nz, ptr(per), len(w32), ptr(off), ptr(w32), int(T),
+                          _STORAGE_CODE[storage], ptr(flags), ptr(u3), ptr(out))
+    if rc:
+        raise RuntimeError(f"emu_sweep failed ({rc})")
+    return out[0] if two_d else out
+
+
+def sweep_bits_box_from_field(u0, offsets, weights, T, box_lo, box_hi, storage="f32",
+                              periodic=(0, 0, 0), round_after=None):
+    """sweep_bits restricted to the sub-box [box_lo, box_hi) ((x, y, z)
+    triples) of a field of any size (numpy array or torch CPU tensor of the
+    storage type, (z, y, x)); only the box's dependency cone is read.
+    Returns FP32 values shaped (z, y, x)."""
+    from .oracle import _lib, extract_window, reach_of
+    shape = tuple(u0.shape) if len(u0.shape) == 3 else (1,) + tuple(u0.shape)
+    nx, ny, nz = shape[2], shape[1], shape[0]
+    off, w32, per, flags, ptr = _c_args(offsets, weights, periodic, T, round_after)
+    reach = np.asarray(reach_of(off))
+    lo = np.ascontiguousarray(np.asarray(box_lo, dtype=np.int64).reshape(3))
+    hi = np.ascontiguousarray(np.asarray(box_hi, dtype=np.int64).reshape(3))
+    win = np.ascontiguousarray(extract_window(u0, lo - T * reach, hi + T * reach, per)
+                               .astype(np.float32))
+    e = hi - lo
+    out = np.empty((e[2], e[1], e[0]), np.float32)
+    rc = _lib().emu_sweep_box_win(nx, ny, nz, ptr(per), len(w32), ptr(off), ptr(w32), int(T),
+                                  _STORAGE_CODE[storage], ptr(flags), ptr(win), ptr(lo),
+                                  ptr(hi), ptr(out))
+    if rc:
+        raise RuntimeError(f"emu_sweep_box_win failed ({rc})")
+    return out

@@ -32,8 +32,8 @@ def _lib():
     global _LIB
     if _LIB is None:
         p = lib_path()
-        src = os.path.join(_HERE, "so2dr_oracle.c")
-        if not os.path.exists(p) or os.path.getmtime(p) < os.path.getmtime(src):
+        srcs = [os.path.join(_HERE, f) for f in ("so2dr_oracle.c", "emulator_bits.c")]
+        if not os.path.exists(p) or os.path.getmtime(p) < max(os.path.getmtime(s) for s in srcs):
             build()
         L = ctypes.CDLL(p)
         i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
@@ -43,8 +43,11 @@ def _lib():
                                      vp, vp, vp, vp]
         L.oracle_sweep_box.argtypes = [i64, i64, i64, vp, i32, vp, vp, i32, vp, vp, vp, vp]
         L.oracle_sweep_box_win.argtypes = [i64, i64, i64, vp, i32, vp, vp, i32, vp, vp, vp, vp]
+        L.emu_sweep.argtypes = [i64, i64, i64, vp, i32, vp, vp, i32, i32, vp, vp, vp]
+        L.emu_sweep_box_win.argtypes = [i64, i64, i64, vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
+                                        vp]
         for f in (L.oracle_sweep, L.oracle_transpose_step, L.oracle_adjoint, L.oracle_sweep_box,
-                  L.oracle_sweep_box_win):
+                  L.oracle_sweep_box_win, L.emu_sweep, L.emu_sweep_box_win):
             f.restype = i32
         _LIB = L
     return _LIB
