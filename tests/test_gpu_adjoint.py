@@ -169,3 +169,40 @@ def test_stencil_loss_autograd():
     assert abs(L.item() - rl) <= 1e-5 * rl
     assert rel_l2(u0.grad.double().numpy(), 2 * rgu) <= 1e-4
     assert _gw_err(w.grad.numpy(), 2 * rgw) <= 1e-4
+
+
+def test_adjoint_256cube_per_component_vs_fp64_reference():
+    """The gradient workload's form at 256^3: 7-point weights 0.4 / 0.1,
+    T = 128, host checkpoints every 16 steps, K = 8, 4 or more chunks, FP32
+    storage; target from the same sweep with perturbed weights.  The loss,
+    every dL/dw_k (per component, |g - g_ref| / max(|g_ref|, 1e-3
+    ||g_ref||_inf)) and dL/du0 (relative L2) against the FP64 oracle's full
+    reverse sweep, each within 1e-4."""
+    offs = oracle.stencil_offsets(3, "star", 1)
+    w = fp32_weights(workloads.centre_arm_weights(offs, 0.4, [0.1]))
+    wt = fp32_weights(workloads.perturbed(w, 50))
+    n, T = 256, 128
+    u0n = workloads.uniform((n, n, n), seed=5).astype(np.float32).astype(np.float64)
+    u0 = to_storage(u0n, "f32")
+    yh = pinned_copy(u0)
+    pt = Plan(ndim=3, nx=n, ny=n, nz=n, shape="star", radius=1, weights=list(wt), T=T, tb_depth=8,
+              n_chunks=4, budget=1 << 30).bind()
+    pt.run(yh)
+    pt.close()
+    kw = dict(ndim=3, nx=n, ny=n, nz=n, shape="star", radius=1, weights=list(w), T=T, tb_depth=8,
+              n_chunks=0, budget=160 << 20)
+    p = Plan(adjoint=True, **kw)
+    info = p.info()
+    p.close()
+    assert info["n_chunks"] >= 4 and info["tb_depth"] == 8, info
+    loss, gu, gw, st = _run_adjoint(kw, u0, yh, 16)
+    rl, rgu, rgw, _ = oracle.adjoint(u0n, yh.double().numpy(), offs, w, T, ckpt=16)
+    e_loss = abs(loss - rl) / abs(rl)
+    e_gu = rel_l2(gu.double().numpy(), rgu)
+    den = np.maximum(np.abs(rgw), 1e-3 * np.abs(rgw).max())
+    e_comp = np.abs(np.asarray(gw) - rgw) / den
+    print(f"[256^3 T=128, {info['n_chunks']} chunks, {info['n_slots']} slots] loss {e_loss:.2e}, "
+          f"grad_u0 rel L2 {e_gu:.2e}, grad_w per component " +
+          " ".join(f"{e:.1e}" for e in e_comp), flush=True)
+    assert e_loss <= 1e-4 and e_gu <= 1e-4
+    assert np.all(e_comp <= 1e-4), e_comp

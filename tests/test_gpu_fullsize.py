@@ -1,8 +1,9 @@
-"""Parity at the workloads' full sizes, in the launch configuration the
-benchmark uses: sampled output boxes against the FP64 oracle's light-cone
-sub-box sweep (it reads only each box's dependency cone of u0), bit-for-bit
-in-core vs out-of-core where two fields fit in HBM, and for the adjoint,
-identities that hold at any size.
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark uses and in the plans the cost model picks: sampled output boxes
+against the FP64 oracle's light-cone sub-box sweep (it reads only each box's
+dependency cone of u0) and bit for bit against the C model of the documented
+arithmetic, bit-for-bit in-core vs out-of-core for every plan and storage
+type, and for the adjoint, identities that hold at any size.
 
 Large pinned host fields: 2D 5-point 1024^2; 3D 7-point and 27-point
 2048x1024x1024 (8 GiB per FP32 field); 13-point 2048^3 (32 GiB FP32);
@@ -126,7 +127,27 @@ def test_c1_2d5pt_full():
     assert torch.equal(hi, h)
 
 
-def _full_3d(name, k_on=0):
+def _check_bits(u0_np, got_np, offs, w, T, per, boxes, storage, tag):
+    """Sampled boxes bit for bit against the C model of the documented
+    arithmetic (light-cone windows; the grid's interior boxes come from the
+    kernels' interior path)."""
+    from oracle import emulator
+    for lo, hi in boxes:
+        ref = emulator.sweep_bits_box_from_field(u0_np, offs, w, T, lo, hi, storage, per)
+        g = got_np[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        g = np.ascontiguousarray(g.float().numpy() if isinstance(g, torch.Tensor) else g,
+                                 dtype=np.float32)
+        diff = int(np.sum(g.view(np.uint32) != ref.view(np.uint32)))
+        assert diff == 0, f"{tag}: box {lo}-{hi}: {diff} cells differ from the arithmetic model"
+    _log(f"{tag}: {len(boxes)} boxes bit-identical to the arithmetic model")
+
+
+def _full_3d(name, plans):
+    """The workload's field, run out of core under each plan of `plans`
+    (keyword overrides of the workload's tb_depth / n_chunks / k_on /
+    n_slots), checked on sampled boxes against the FP64 oracle and bit for
+    bit against the arithmetic model, and each bit for bit against the
+    in-core run."""
     wl = WL[name]
     offs = stencil_offsets(3, wl.shape, wl.radius)
     w = workloads.fp32_rounded(_weights(wl, offs))
@@ -140,65 +161,116 @@ def _full_3d(name, k_on=0):
     _log(f"{name}: input ready in {time.time() - t0:.1f} s")
     kw = dict(ndim=3, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
               weights=list(w), T=wl.T, bc=wl.periodic)
-    p = Plan(tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, k_on=k_on, budget=wl.budget, **kw).bind()
-    info = p.info()
-    assert info["workspace_bytes"] <= wl.budget
-    h_out = _pinned(shp, torch.float32)
-    st = p.run_steps(h_in, h_out, wl.T)
-    p.close()
-    _log(f"{name}: out-of-core {st['wall_ms']:.0f} ms, {info['n_chunks']} chunks, "
-         f"{info['n_slots']} slots, k_on {info['k_on']}")
-    rng = np.random.default_rng(7)
-    boxes = _sample_boxes(wl.nx, wl.ny, wl.nz, info["n_chunks"], rng)
-    _check_boxes(h_in.numpy(), h_out.numpy(), offs, w, wl.T, wl.periodic, boxes, 1e-5, name)
-    # bit-for-bit against the in-core run (two 8 GiB fields fit in HBM)
     pin = Plan(tb_depth=wl.T, n_chunks=1, budget=24 << 30, **kw).bind()
     h_ic = _pinned(shp, torch.float32)
     pin.run_steps(h_in, h_ic, wl.T)
     pin.close()
-    assert torch.equal(h_ic, h_out), f"{name}: out-of-core differs from in-core"
-    _log(f"{name}: out-of-core == in-core bit for bit")
+    h_out = _pinned(shp, torch.float32)
+    rng = np.random.default_rng(7)
+    uniq = []
+    for over in plans:   # suggest() may pick a plan already listed
+        if over not in uniq:
+            uniq.append(over)
+    for i, over in enumerate(uniq):
+        plan_kw = dict(dict(tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, k_on=0, n_slots=0,
+                            budget=wl.budget), **over)
+        p = Plan(**plan_kw, **kw).bind()
+        info = p.info()
+        assert info["workspace_bytes"] <= wl.budget
+        for k in ("tb_depth", "n_chunks", "k_on", "n_slots"):
+            if over.get(k):
+                assert info[k] == over[k], (k, info[k], over[k])
+        st = p.run_steps(h_in, h_out, wl.T)
+        p.close()
+        tag = (f"{name} K={info['tb_depth']} d={info['n_chunks']} k_on={info['k_on']} "
+               f"slots={info['n_slots']}")
+        _log(f"{tag}: out-of-core {st['wall_ms']:.0f} ms")
+        assert torch.equal(h_ic, h_out), f"{tag}: out-of-core differs from in-core"
+        _log(f"{tag}: out-of-core == in-core bit for bit")
+        if i == 0:
+            boxes = _sample_boxes(wl.nx, wl.ny, wl.nz, info["n_chunks"], rng)
+            _check_boxes(h_in.numpy(), h_out.numpy(), offs, w, wl.T, wl.periodic, boxes, 1e-5, name)
+            _check_bits(h_in.numpy(), h_out.numpy(), offs, w, wl.T, wl.periodic, boxes, "f32", name)
+
+
+def _suggested(name):
+    """The plan so2dr_plan_suggest picks for the workload with the round
+    depth, chunk count, fused depth and slot count all free."""
+    from paper_2309_08864_amd import suggest
+    wl = WL[name]
+    offs = stencil_offsets(3, wl.shape, wl.radius)
+    w = workloads.fp32_rounded(_weights(wl, offs))
+    kw, pred = suggest(ndim=3, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
+                       weights=list(w), T=wl.T, budget=wl.budget, bc=wl.periodic)
+    auto = {k: kw[k] for k in ("tb_depth", "n_chunks", "k_on", "n_slots")}
+    _log(f"{name}: suggest() -> {auto}, predicted {pred:.0f} ms")
+    return auto
 
 
 def test_c2_3d7pt_full():
-    _full_3d("c2_3d7pt")
+    """The benchmark's plan (K = 8, 16 chunks, k_on = 3, 3 slots); the cost
+    model's plan with the round depth free as measured (K = 24, 16 chunks,
+    k_on = 3, 2 slots: 64-plane chunks carrying a 48-plane halo); and
+    whatever so2dr_plan_suggest picks now."""
+    _full_3d("c2_3d7pt", [{}, dict(tb_depth=24, n_chunks=16, k_on=3, n_slots=2),
+                          _suggested("c2_3d7pt")])
 
 
 def test_c3_3d27pt_full():
-    _full_3d("c3_3d27pt")
+    """The workload's plan (K = 4, 16 chunks); the cost model's measured plan
+    (K = 16, 29 ragged chunks, k_on = 2, 3 slots); and what so2dr_plan_suggest
+    picks now."""
+    _full_3d("c3_3d27pt", [{}, dict(tb_depth=16, n_chunks=29, k_on=2, n_slots=3),
+                           _suggested("c3_3d27pt")])
 
 
 def test_c4_3d13pt_full_precision():
-    """2048^3 13-point star, BF16 then FP16 then FP32 storage, in place.  The
-    FP32 field (FP64 recipe rounded once) is the reference input; the BF16 /
-    FP16 inputs are its roundings.  Each storage type is checked on sampled
-    boxes against the oracle run from its own input (arithmetic error, must
-    stay under the per-step rounding bound) and reported against the FP32
-    input's oracle result (total error)."""
+    """2048^3 13-point star in BF16, FP16 and FP32 storage (the FP32 field,
+    from the FP64 recipe rounded once, is the input; BF16 / FP16 inputs are
+    its roundings).  Per storage type: the workload's plan (K = 8, 32 chunks)
+    and, for FP32, also the cost model's plan (K = 24, 19 chunks, 1 slot)
+    are bit-identical to the in-core run of that type; sampled boxes are
+    bit-identical to the arithmetic model and, against the FP64 oracle run
+    from the same input, within the rigorous per-step rounding bound; the
+    error against the oracle run from the FP32 input is reported.  At most
+    one field (32 GiB) is pinned at a time; the input and the out-of-core
+    result are kept in pageable memory."""
+    import gc
     wl = WL["c4_3d13pt"]
     offs = stencil_offsets(3, "star", 2)
     w = workloads.fp32_rounded(_weights(wl, offs))
     shp = (wl.nz, wl.ny, wl.nx)
-    h32 = _pinned(shp, torch.float32)
+    master = np.empty(shp, np.float32)
     t0 = time.time()
-    workloads.gaussian_bump_into(h32.numpy(), wl.seed)
+    workloads.gaussian_bump_into(master, wl.seed)
+    tm = torch.from_numpy(master)
     _log(f"c4: input ready in {time.time() - t0:.1f} s")
-    max_u0 = float(h32.abs().max())
+    max_u0 = max(float(master.max()), -float(master.min()))
     rng = np.random.default_rng(11)
     boxes = _sample_boxes(wl.nx, wl.ny, wl.nz, 32, rng, size=2, extra=3)
-    refs32 = [oracle.sweep_box_from_field(h32.numpy(), offs, w, wl.T, lo, hi) for lo, hi in boxes]
+    refs32 = [oracle.sweep_box_from_field(master, offs, w, wl.T, lo, hi) for lo, hi in boxes]
     base = dict(ndim=3, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape="star", radius=2, weights=list(w),
-                T=wl.T, tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, budget=wl.budget)
+                T=wl.T)
+    dts = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32}
+    for name in ("bf16", "f16", "f32"):
+        h = _pinned(shp, dts[name])
 
-    def check(name, t, refs_own):
-        p = Plan(storage=name, **base).bind()
-        st = p.run(t)
+        def load():
+            for z0 in range(0, wl.nz, 64):
+                h[z0:z0 + 64].copy_(tm[z0:z0 + 64])
+
+        load()
+        refs_own = refs32 if name == "f32" else \
+            [oracle.sweep_box_from_field(h, offs, w, wl.T, lo, hi) for lo, hi in boxes]
+        p = Plan(storage=name, tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, budget=wl.budget,
+                 **base).bind()
+        st = p.run(h)
         p.close()
-        _log(f"c4 {name}: {st['wall_ms']:.0f} ms")
-        worst_arith, worst_total = 0.0, 0.0
+        _log(f"c4 {name} K=8 d=32: {st['wall_ms']:.0f} ms")
         unit = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}[name]
-        for (lo, hi), r32, ref_own in zip(boxes, refs32, refs_own):
-            g = t[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].double().numpy()
+        worst_arith, worst_total = 0.0, 0.0
+        for k, ((lo, hi), r32, ref_own) in enumerate(zip(boxes, refs32, refs_own)):
+            g = h[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].double().numpy()
             worst_total = max(worst_total, rel_l2(g, r32))
             err = np.abs(g - ref_own).max()
             # weights >= 0 summing to 1: ||A||_inf <= 1, so the error is at most
@@ -208,22 +280,33 @@ def test_c4_3d13pt_full_precision():
             assert err <= bound, f"c4 {name}: box {lo} max err {err:.3e} > bound {bound:.3e}"
         _log(f"c4 {name}: worst total rel L2 vs FP64 oracle (FP32 input) {worst_total:.3e}; "
              f"worst arithmetic max err {worst_arith:.3e}")
-        return worst_total
-
-    # reduced storage first, one field at a time (its input is the FP32 field
-    # rounded once), so that at most 48 GiB are pinned; FP32 last, in place
-    import gc
-    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
-        t = _pinned(shp, dt)
-        for z0 in range(0, wl.nz, 64):
-            t[z0:z0 + 64].copy_(h32[z0:z0 + 64])
-        refs_own = [oracle.sweep_box_from_field(t, offs, w, wl.T, lo, hi) for lo, hi in boxes]
-        check(name, t, refs_own)
-        del t
+        if name == "f32":
+            assert worst_total <= 1e-5
+        ooc = h.clone()                  # pageable copy of the out-of-core result
+        load()
+        _check_bits(h, ooc, offs, w, wl.T, (0, 0, 0), boxes, name, f"c4 {name}")
+        if name == "f32":
+            p = Plan(storage=name, tb_depth=24, n_chunks=19, k_on=2, n_slots=1, budget=wl.budget,
+                     **base).bind()
+            info = p.info()
+            assert (info["tb_depth"], info["n_chunks"], info["n_slots"]) == (24, 19, 1)
+            st = p.run(h)
+            p.close()
+            _log(f"c4 f32 K=24 d=19 1 slot: {st['wall_ms']:.0f} ms")
+            assert torch.equal(h, ooc), "c4 f32: the cost model's plan differs from K=8 d=32"
+            load()
+        esz = h.element_size()
+        pin = Plan(storage=name, tb_depth=wl.T, n_chunks=1,
+                   budget=2 * wl.nx * wl.ny * wl.nz * esz + (2 << 30), **base).bind()
+        st = pin.run(h)
+        pin.close()
+        _log(f"c4 {name} in-core: {st['wall_ms']:.0f} ms")
+        assert torch.equal(h, ooc), f"c4 {name}: out-of-core differs from in-core"
+        _log(f"c4 {name}: out-of-core == in-core bit for bit")
+        del h, ooc
         gc.collect()
         if hasattr(torch._C, "_host_emptyCache"):
             torch._C._host_emptyCache()
-    assert check("f32", h32, refs32) <= 1e-5
 
 
 def test_c5_adjoint_full():
