@@ -20,8 +20,12 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(os.path.dirname(HERE), "include"), "-Wall", "-Wno-unused-function"]
 
-SOURCES = ["kernels_f32.hip", "kernels_f64.hip", "kernels_bf16.hip", "kernels_f16.hip",
-           "aux_kernels.hip", "planner.cpp", "runtime.cpp", "adjoint.cpp", "model.cpp", "capi.cpp"]
+# (source, extra compiler flags, object name): kernels.hip is compiled once
+# per storage type (so2dr_dtype value in SO2DR_STORAGE)
+SOURCES = [("kernels.hip", [f"-DSO2DR_STORAGE={d}"], f"kernels_{name}.o")
+           for d, name in ((0, "f32"), (1, "f64"), (2, "bf16"), (3, "f16"))]
+SOURCES += [(s, [], s + ".o") for s in ("aux_kernels.hip", "planner.cpp", "runtime.cpp",
+                                         "adjoint.cpp", "model.cpp", "capi.cpp")]
 
 
 def _deps_mtime(src: str) -> float:
@@ -34,12 +38,13 @@ def _deps_mtime(src: str) -> float:
     return max(os.path.getmtime(f) for f in files)
 
 
-def _compile(src: str, incremental: bool = False) -> str:
+def _compile(entry, incremental: bool = False) -> str:
+    src, flags, objname = entry
     path = os.path.join(CSRC, src)
-    obj = os.path.join(OBJ, src + ".o")
+    obj = os.path.join(OBJ, objname)
     if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _deps_mtime(src):
         return obj
-    cmd = [HIPCC] + COMMON + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + COMMON + flags + ["-c", path, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,9 +58,8 @@ def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> st
     object newer than its source and every header (a development shortcut;
     the default always recompiles)."""
     os.makedirs(OBJ, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=min(jobs, 16)) as ex:
-        objs = list(ex.map(lambda src: _compile(src, incremental), srcs))
+        objs = list(ex.map(lambda e: _compile(e, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

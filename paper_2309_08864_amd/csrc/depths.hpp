@@ -9,8 +9,8 @@ namespace so2dr {
 constexpr int kMaxDepth[4][ST_COUNT] = {
     /* F32  */ {8, 8, 4, 4, 4, 4, 2, 4},
     /* F64  */ {4, 4, 2, 2, 2, 2, 2, 2},
-    /* BF16 */ {8, 0, 0, 0, 0, 4, 2, 4},
-    /* F16  */ {8, 0, 0, 0, 0, 4, 2, 4},
+    /* BF16 */ {8, 8, 4, 4, 4, 4, 2, 4},
+    /* F16  */ {8, 8, 4, 4, 4, 4, 2, 4},
 };
 
 }  // namespace so2dr

@@ -11,37 +11,12 @@
 #include "star_kernel.hpp"
 #include "tb_kernel.hpp"
 
-#ifndef SO2DR_STAR_KERNEL
-#define SO2DR_STAR_KERNEL 1
-#endif
-#ifndef SO2DR_MARCH_KERNEL
-#define SO2DR_MARCH_KERNEL 1
-#endif
-#ifndef SO2DR_STAR_NW
-#define SO2DR_STAR_NW 8
-#endif
-#ifndef SO2DR_STAR_M
-#define SO2DR_STAR_M 2
-#endif
-#ifndef SO2DR_STAR_VX
-#define SO2DR_STAR_VX 4
-#endif
-#ifndef SO2DR_STAR_HB
-#define SO2DR_STAR_HB 2
-#endif
-
 namespace so2dr {
 
 // Workgroups a launch aims for before it splits the cut axis into segments;
 // each segment re-reads 2*KL*R input planes, so segments stay long.
-#ifndef SO2DR_TARGET_WGS
-#define SO2DR_TARGET_WGS 1024
-#endif
-#ifndef SO2DR_MIN_SEG
-#define SO2DR_MIN_SEG 16
-#endif
-constexpr int64_t kTargetWgs = SO2DR_TARGET_WGS;
-constexpr int64_t kMinSegPlanes = SO2DR_MIN_SEG;
+constexpr int64_t kTargetWgs = 1024;
+constexpr int64_t kMinSegPlanes = 16;
 
 // Segmenting of the cut axis shared by both kernel families: `target`
 // workgroups, never segments shorter than kMinSegPlanes.
@@ -110,19 +85,18 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
     return -1;
   }
   constexpr size_t lds = tb_lds_bytes<T, NDIM, BOX, R, KL>();
-  static bool attr_done = false;
-  if (!attr_done) {
+  // once per instantiation; threads racing here both set the same value
+  static std::atomic<bool> attr_done{false};
+  if (!attr_done.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute((const void *)tb_kernel<T, NDIM, BOX, R, KL, RAS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) {
       if (msg) *msg = std::string("hipFuncSetAttribute: ") + hipGetErrorString(e);
       return -5;
     }
-    attr_done = true;
+    attr_done.store(true, std::memory_order_release);
   }
-  // with the XCD-aware order the grid is padded to a multiple of 8 so that the
-  // permutation covers every tile; padding workgroups exit at once
-  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  const int64_t grid = xcd_grid(nwg);
   hipLaunchKernelGGL((tb_kernel<T, NDIM, BOX, R, KL, RAS>), dim3((unsigned)grid), dim3(G::NT), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -132,8 +106,7 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   return 0;
 }
 
-template <typename T, bool BOX, int R, int KL, int NW = SO2DR_STAR_NW, int M = SO2DR_STAR_M,
-          int VX = SO2DR_STAR_VX, int HB = SO2DR_STAR_HB, bool RAS = false>
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, bool RAS = false>
 int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
   using G = StarTile<R, KL, NW, M, VX>;
@@ -168,7 +141,7 @@ int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) 
     if (msg) *msg = "grid too large for one launch";
     return -1;
   }
-  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  const int64_t grid = xcd_grid(nwg);
   hipLaunchKernelGGL((col3d_kernel<T, BOX, R, KL, NW, M, VX, HB, RAS>), dim3((unsigned)grid), dim3(NW * 64), 0,
                      stream, a);
   hipError_t e = hipGetLastError();
@@ -236,7 +209,7 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
     if (msg) *msg = "grid too large for one launch";
     return -1;
   }
-  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  const int64_t grid = xcd_grid(nwg);
   hipLaunchKernelGGL((march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE, RAS>), dim3((unsigned)grid), dim3(NW * 64), 0,
                      stream, a);
   hipError_t e = hipGetLastError();
@@ -288,7 +261,7 @@ int launch_march2d_one(const LaunchParams &p, hipStream_t stream, std::string *m
     if (msg) *msg = "grid too large for one launch";
     return -1;
   }
-  const int64_t grid = SO2DR_XCD_REMAP ? (nwg + 7) / 8 * 8 : nwg;
+  const int64_t grid = xcd_grid(nwg);
   hipLaunchKernelGGL((march2d_kernel<T, BOX, R, KL, VX, PF, ROT, RAS>), dim3((unsigned)grid), dim3(256), 0, stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -323,13 +296,13 @@ template <typename T, int NDIM, bool BOX, int R, int KL, bool RAS>
 int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
   using A = typename Store<T>::A;
   constexpr size_t kLdsMax = 160 * 1024;
-  if constexpr (NDIM == 2 && SO2DR_MARCH_KERNEL) {
+  if constexpr (NDIM == 2) {
     // unrolling by the stencil width is kept while the unrolled body stays
     // within a few thousand FMAs
     constexpr bool rot = (int64_t)KL * 4 * Stencil<2, BOX, R>::npts() * (2 * R + 1) > 2400;
     if (march_fits<T, 4>(p)) return launch_march2d_one<T, BOX, R, KL, 4, 2, rot, RAS>(p, s, msg);
   }
-  if constexpr (NDIM == 3 && SO2DR_MARCH_KERNEL) {
+  if constexpr (NDIM == 3) {
     constexpr bool wide = KL == 1 && march_lds<A, KL, 16, R, 4, 2>() <= kLdsMax;
     constexpr bool a32 = sizeof(A) == 4;
     constexpr bool square = a32 && !BOX && R == 1 && KL == 2;
@@ -349,9 +322,9 @@ int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
   }
   constexpr size_t lds1 = sizeof(A) * KL * 1 * 16 * 2 * R * 64 * 4;
   constexpr size_t ldsn = sizeof(A) * KL * 2 * 4 * 2 * R * 64 * 1;
-  if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL == 1 && lds1 <= 65536)
+  if constexpr (NDIM == 3 && KL == 1 && lds1 <= 65536)
     return launch_col_one<T, BOX, R, KL, 16, 2, 4, 1, RAS>(p, s, msg);
-  else if constexpr (NDIM == 3 && SO2DR_STAR_KERNEL && KL >= 2 && 2 * KL * R < 32 && ldsn <= 65536)
+  else if constexpr (NDIM == 3 && KL >= 2 && 2 * KL * R < 32 && ldsn <= 65536)
     return launch_col_one<T, BOX, R, KL, 4, 8, 1, 2, RAS>(p, s, msg);
   else
     return launch_one<T, NDIM, BOX, R, KL, RAS>(p, s, msg);

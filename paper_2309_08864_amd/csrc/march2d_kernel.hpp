@@ -163,17 +163,9 @@ __global__ __launch_bounds__(256) void march2d_kernel(const TbArgs<typename Stor
   using G = RowTile<R, KL, VX>;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int wg = blockIdx.x;
   const int ntask = a.ntx * a.nseg;
-#if SO2DR_XCD_REMAP
-  {
-    const int nwg = (ntask + 3) / 4;
-    const int per = (nwg + 7) / 8;
-    const int t = (wg % 8) * per + wg / 8;
-    if (t >= nwg) return;
-    wg = t;
-  }
-#endif
+  const int wg = xcd_tile(blockIdx.x, (ntask + 3) / 4);
+  if (wg < 0) return;
   const int task = wg * 4 + wave;
   if (task >= ntask) return;
   const int tx_i = task % a.ntx, seg = task / a.ntx;

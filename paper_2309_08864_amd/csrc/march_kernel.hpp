@@ -10,8 +10,9 @@
 //     modulo 2R+1; the march loop is unrolled by 2R+1 steps, so every ring
 //     index is a compile-time constant and nothing is moved between
 //     registers.  An output's first term starts its sum from +0 directly;
-//   * prefetched input planes sit in a ring of the same width (plane p in
-//     slot p mod 2R+1), loaded PF steps ahead without conditions: the plane
+//   * prefetched input planes sit in a ring of RS slots, RS the smallest
+//     multiple of 2R+1 above PF (plane p in slot p mod RS; the march is
+//     unrolled by RS), loaded PF steps ahead without conditions: the plane
 //     index is clamped into the buffer's valid planes and every lane reads an
 //     in-grid address (ghost columns and rows read a clamped or wrapped one),
 //     so a load's destination is the ring register itself.  Ghost values are
@@ -62,16 +63,8 @@ __global__ __launch_bounds__(NW * 64, WPE) void march3d_kernel(const TbArgs<type
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  int wg = blockIdx.x;
-#if SO2DR_XCD_REMAP
-  {
-    const int nwg = a.ntx * a.nty * a.nseg;
-    const int per = (nwg + 7) / 8;
-    const int t = (wg % 8) * per + wg / 8;
-    if (t >= nwg) return;
-    wg = t;
-  }
-#endif
+  int wg = xcd_tile(blockIdx.x, a.ntx * a.nty * a.nseg);
+  if (wg < 0) return;
   const int tx_i = wg % a.ntx;
   wg /= a.ntx;
   const int ty_i = wg % a.nty;
@@ -102,7 +95,8 @@ __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> 
   using S = Stencil<3, BOX, R>;
   using G = StarTile<R, KL, NW, M, VX>;
   constexpr int W = 2 * R + 1;
-  static_assert(PF >= 1 && PF < W, "prefetch distance must leave the consumed slot alone");
+  constexpr int RS = W * (PF / W + 1);  // prefetch ring: a multiple of W above PF
+  static_assert(PF >= 1 && PF < RS, "prefetch distance must leave the consumed slot alone");
   const int P0 = zo0 - KL * R;
   const int n_axis = (int)a.n_axis;
   const int p_lo = max((int)a.in_lo, 0), p_hi = min((int)a.in_hi, n_axis) - 1;  // loadable planes
@@ -136,7 +130,7 @@ __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> 
 
   A acc[KL][M][VX][W];  // acc[l][m][j][o mod W]: partial sum of output plane o
   A done[KL][M][VX];    // newest completed plane of levels 1..KL-1
-  A ring[W][M][VX];     // input plane P0 + p in slot p mod W
+  A ring[RS][M][VX];    // input plane P0 + p in slot p mod RS
 #pragma unroll
   for (int l = 0; l < KL; ++l)
 #pragma unroll
@@ -152,7 +146,7 @@ __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> 
   const int n_load = span + 2 * KL * R;
   // steps past the last useful one are no-ops for every level, so the count
   // is rounded up to whole unrolled groups
-  const int n_steps = (n_load + KL - 1 + W - 1) / W * W;
+  const int n_steps = (n_load + KL - 1 + RS - 1) / RS * RS;
 
   auto load_plane = [&](int p, A (*dst)[VX]) {
     const int pc = min(max(p, p_lo), p_hi);
@@ -166,12 +160,12 @@ __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> 
   const int wu = wave > 0 ? wave - 1 : 0;  // clamped: rows beyond the tile are never valid
   const int wd = wave < NW - 1 ? wave + 1 : NW - 1;
 
-  // one march step; s = PH (mod W)
+  // one march step; s = PH (mod RS), so also s = PH (mod W)
   auto step = [&](auto ph_c, int s) {
     constexpr int PH = decltype(ph_c)::value;
     const int b = HB == 2 ? (s & 1) : 0;
     if (HB == 1) __syncthreads();  // the previous step's halo reads are done
-    load_plane(P0 + s + PF, ring[(PH + PF) % W]);
+    load_plane(P0 + s + PF, ring[(PH + PF) % RS]);
     if constexpr (GH) {  // ghosts of the plane consumed now
       const bool zg = P0 + s < 0 || P0 + s >= n_axis;
 #pragma unroll
@@ -270,8 +264,8 @@ __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> 
         std::make_integer_sequence<int, KL>{});
   };
 
-  for (int s = 0; s < n_steps; s += W)
-    unroll_seq([&](auto ph) { step(ph, s + decltype(ph)::value); }, std::make_integer_sequence<int, W>{});
+  for (int s = 0; s < n_steps; s += RS)
+    unroll_seq([&](auto ph) { step(ph, s + decltype(ph)::value); }, std::make_integer_sequence<int, RS>{});
 }
 
 }  // namespace so2dr

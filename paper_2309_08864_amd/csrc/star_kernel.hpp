@@ -139,16 +139,8 @@ __global__ __launch_bounds__(NW * 64) void col3d_kernel(const TbArgs<typename St
   T *__restrict__ out = static_cast<T *>(a.out);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-  int wg = blockIdx.x;
-#if SO2DR_XCD_REMAP
-  {
-    const int nwg = a.ntx * a.nty * a.nseg;
-    const int per = (nwg + 7) / 8;
-    const int t = (wg % 8) * per + wg / 8;
-    if (t >= nwg) return;
-    wg = t;
-  }
-#endif
+  int wg = xcd_tile(blockIdx.x, a.ntx * a.nty * a.nseg);
+  if (wg < 0) return;
   const int tx_i = wg % a.ntx;
   wg /= a.ntx;
   const int ty_i = wg % a.nty;

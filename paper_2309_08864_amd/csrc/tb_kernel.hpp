@@ -35,17 +35,21 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
-#ifndef SO2DR_XCD_REMAP
-#define SO2DR_XCD_REMAP 1
-#endif
-#ifndef SO2DR_PREFETCH2
-#define SO2DR_PREFETCH2 0
-#endif
-#ifndef SO2DR_NT_STORE
-#define SO2DR_NT_STORE 0
-#endif
-
 namespace so2dr {
+
+// Workgroup order.  Consecutive workgroups are dealt round-robin to the 8
+// XCDs, each with its own L2; remapping gives each XCD a contiguous run of
+// tiles, so neighbouring tiles' shared halo columns are fetched through the
+// same L2.  The grid is padded to a multiple of 8 (xcd_grid) so that the
+// permutation covers every tile; xcd_tile returns -1 for padding
+// workgroups, which exit at once.
+constexpr int kXcds = 8;
+__host__ __device__ constexpr int64_t xcd_grid(int64_t nwg) { return (nwg + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_tile(int wg, int nwg) {
+  const int per = (nwg + kXcds - 1) / kXcds;
+  const int t = (wg % kXcds) * per + wg / kXcds;
+  return t < nwg ? t : -1;
+}
 
 constexpr int kMaxPts = 81;  // 2D box of radius 4
 
@@ -151,11 +155,7 @@ template <int NDIM, int R, int KL>
 struct Tile {
   static constexpr int NT = 256;
   static constexpr int TX = NDIM == 2 ? (R >= 3 ? 512 : 1024) : 64;
-#ifdef SO2DR_TY
-  static constexpr int TY = NDIM == 2 ? 1 : (KL * R <= 2 ? SO2DR_TY : 32);
-#else
   static constexpr int TY = NDIM == 2 ? 1 : (KL * R <= 2 ? 16 : 32);
-#endif
   static constexpr int RY = NDIM == 3 ? R : 0;
   static constexpr int NC = TX * TY / NT;  // cells per lane
   static constexpr int LX = TX + 2 * R;    // LDS row, padded by R each side
@@ -181,19 +181,8 @@ __global__ __launch_bounds__(256) void tb_kernel(const TbArgs<typename Store<T>:
   T *__restrict__ out = static_cast<T *>(a.out);
 
   // workgroup -> (tile x, tile y, segment)
-  int wg = blockIdx.x;
-#if SO2DR_XCD_REMAP
-  {
-    // consecutive workgroups are dealt round-robin to the 8 XCDs; give each
-    // XCD a contiguous run of tiles so neighbouring tiles' shared halo
-    // columns are fetched through the same L2
-    const int nwg = a.ntx * a.nty * a.nseg;
-    const int per = (nwg + 7) / 8;
-    const int t = (wg % 8) * per + wg / 8;
-    if (t >= nwg) return;
-    wg = t;
-  }
-#endif
+  int wg = xcd_tile(blockIdx.x, a.ntx * a.nty * a.nseg);
+  if (wg < 0) return;
   const int tx_i = wg % a.ntx;
   wg /= a.ntx;
   const int ty_i = wg % a.nty;
@@ -253,13 +242,7 @@ __global__ __launch_bounds__(256) void tb_kernel(const TbArgs<typename Store<T>:
     for (int c = 0; c < NC; ++c) dst[c] = (ok && !ghost[c]) ? Store<T>::load(base + goff[c]) : A(0);
   };
 
-#if SO2DR_PREFETCH2
-  A nxt2[NC];
   load_plane(P0, nxt);
-  load_plane(P0 + 1, nxt2);
-#else
-  load_plane(P0, nxt);
-#endif
 
   for (int64_t m = 0; m < n_steps; ++m) {
     const int b = (int)(m & 1);
@@ -268,13 +251,7 @@ __global__ __launch_bounds__(256) void tb_kernel(const TbArgs<typename Store<T>:
       A *dst = lds + (0 * 2 + b) * G::LPLANE;
 #pragma unroll
       for (int c = 0; c < NC; ++c) dst[lidx[c]] = nxt[c];
-#if SO2DR_PREFETCH2
-#pragma unroll
-      for (int c = 0; c < NC; ++c) nxt[c] = nxt2[c];
-      if (m + 2 < n_load) load_plane(P0 + m + 2, nxt2);
-#else
       if (m + 1 < n_load) load_plane(P0 + m + 1, nxt);
-#endif
     }
 #pragma unroll
     for (int l = 1; l < KL; ++l) {
@@ -324,11 +301,7 @@ __global__ __launch_bounds__(256) void tb_kernel(const TbArgs<typename Store<T>:
         if (l < KL) {
           done[l][c] = res;
         } else if (outc[c] && q >= zo0 && q < zo1) {
-#if SO2DR_NT_STORE
-          __builtin_nontemporal_store(res, out + (q - a.out_z0) * a.plane + goff[c]);
-#else
           Store<T>::store(out + (q - a.out_z0) * a.plane + goff[c], res);
-#endif
         }
       }
     }
