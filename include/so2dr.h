@@ -182,6 +182,11 @@ typedef struct {
   uint64_t cell_updates_done;  /* including the redundant halo recomputation */
   uint64_t kernel_alg_bytes;   /* sum over launches of (input area + output area) * elem size */
   int rounds_done;
+  /* the kernel figures split by fused depth: entry l-1 for launches of l
+   * levels (kernel_ms_by_levels only with timing enabled) */
+  double kernel_ms_by_levels[8];
+  uint64_t launches_by_levels[8];
+  uint64_t alg_bytes_by_levels[8];
 } so2dr_stats;
 
 /* Validate the descriptor and build the plan: chunk bounds, per-round depth
@@ -204,6 +209,19 @@ int so2dr_plan_workspace_bytes(const struct so2dr_plan *plan, size_t *bytes);
 
 /* Copy the first n entries of the schedule into ops (host-only; n <= info.n_ops). */
 int so2dr_plan_get_ops(const struct so2dr_plan *plan, so2dr_op *ops, int64_t n);
+
+/* How the executor runs the schedule on n_streams streams (host-only; the
+ * rules of so2dr_run and so2dr_run_steps, computed by the same code): op k
+ * of so2dr_plan_get_ops is enqueued on stream index stream[k] (roles as in
+ * so2dr_plan_bind) after waiting for the completion of the earlier ops
+ * waits[k * SO2DR_MAX_WAITS + i] (-1 = none; ops on one stream also run in
+ * list order).  The waits are what make the pipeline of Algorithm 1 safe:
+ * slot reuse, copy-in before compute before copy-out, the region-sharing
+ * buffer read before it is overwritten, and the in-place host array across
+ * rounds.  n <= info.n_ops entries are written.  Errors: E_INVALID. */
+#define SO2DR_MAX_WAITS 4
+int so2dr_plan_get_deps(const struct so2dr_plan *plan, int n_streams, int32_t *stream,
+                        int64_t *waits, int64_t n);
 
 /* Attach device memory and streams.  dev_arena: device pointer to at least
  * so2dr_plan_workspace_bytes bytes, 256-byte aligned, owned by the caller and
@@ -297,6 +315,21 @@ int so2dr_plan_predict(const struct so2dr_plan *plan, const so2dr_machine *m, in
  * validation error, or E_BUDGET when no candidate fits. */
 int so2dr_plan_suggest(const so2dr_desc *desc, const so2dr_machine *m, so2dr_desc *out,
                        double *ms);
+
+/* Time one fused-step launch of the plan's stencil and storage type on
+ * device memory the caller owns (measurement; the rates behind the cost
+ * model's per-depth figures and the kernels' roofline positions).  dev_in,
+ * dev_out: device buffers of in_planes planes each (plane = nx * ny elements
+ * of the storage type); dev_in is read as an interior chunk of the cut axis
+ * (the planes in its middle), and the launch advances it by `levels` steps
+ * into planes [levels * radius, in_planes - levels * radius) of dev_out.
+ * levels == 0 times the library's device copy kernel over the in_planes
+ * planes instead.  One untimed launch, then `reps` launches back to back on
+ * `stream` between two HIP events; *ms receives the mean time per launch.
+ * Errors: E_INVALID (levels outside [0, max_k_on], in_planes <= 2 levels r
+ * or beyond the cut axis, null pointers, reps < 1), E_UNSUPPORTED, E_HIP. */
+int so2dr_kernel_bench(const struct so2dr_plan *plan, int levels, void *dev_in, void *dev_out,
+                       int64_t in_planes, int reps, void *stream, double *ms);
 
 /* Message describing the last error on this thread ("" if none). */
 const char *so2dr_last_error(void);

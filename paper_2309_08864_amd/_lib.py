@@ -23,7 +23,11 @@ EXPORTS = ["so2dr_plan_create", "so2dr_plan_destroy", "so2dr_plan_get_info",
            "so2dr_plan_workspace_bytes", "so2dr_plan_get_ops", "so2dr_plan_bind",
            "so2dr_plan_set_timing", "so2dr_run", "so2dr_run_steps", "so2dr_adjoint_run",
            "so2dr_last_error", "so2dr_version", "so2dr_machine_default", "so2dr_plan_predict",
-           "so2dr_plan_suggest", "so2dr_host_alloc", "so2dr_host_free"]
+           "so2dr_plan_suggest", "so2dr_host_alloc", "so2dr_host_free",
+           "so2dr_plan_get_deps", "so2dr_kernel_bench"]
+
+MAX_WAITS = 4   # SO2DR_MAX_WAITS
+
 
 
 class Desc(ctypes.Structure):
@@ -73,10 +77,13 @@ class Stats(ctypes.Structure):
                 ("bytes_d2h", ctypes.c_uint64), ("bytes_d2d", ctypes.c_uint64),
                 ("kernel_launches", ctypes.c_uint64), ("cell_updates", ctypes.c_uint64),
                 ("cell_updates_done", ctypes.c_uint64), ("kernel_alg_bytes", ctypes.c_uint64),
-                ("rounds_done", ctypes.c_int)]
+                ("rounds_done", ctypes.c_int), ("kernel_ms_by_levels", ctypes.c_double * 8),
+                ("launches_by_levels", ctypes.c_uint64 * 8),
+                ("alg_bytes_by_levels", ctypes.c_uint64 * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: (list(getattr(self, k)) if k.endswith("_by_levels") else getattr(self, k))
+                for k, _ in self._fields_}
 
 
 _LIB = None
@@ -96,6 +103,10 @@ def lib():
         L.so2dr_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.so2dr_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.so2dr_plan_get_ops.argtypes = [vp, ctypes.POINTER(Op), i64]
+        L.so2dr_plan_get_deps.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(i64), i64]
+        L.so2dr_kernel_bench.argtypes = [vp, i32, vp, vp, i64, i32, vp,
+                                         ctypes.POINTER(ctypes.c_double)]
         L.so2dr_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp), i32]
         L.so2dr_plan_set_timing.argtypes = [vp, i32]
         L.so2dr_run.argtypes = [vp, vp, ctypes.POINTER(Stats)]
@@ -116,7 +127,8 @@ def lib():
                   "so2dr_plan_get_ops", "so2dr_plan_bind", "so2dr_plan_set_timing", "so2dr_run",
                   "so2dr_run_steps", "so2dr_adjoint_run", "so2dr_machine_default",
                   "so2dr_plan_predict", "so2dr_plan_suggest", "so2dr_host_alloc",
-                  "so2dr_host_free"):
+                  "so2dr_host_free", "so2dr_plan_get_deps",
+                  "so2dr_kernel_bench"):
             getattr(L, f).restype = i32
         _LIB = L
     return _LIB

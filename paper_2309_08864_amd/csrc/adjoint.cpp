@@ -277,8 +277,8 @@ static int reverse_round(Plan &P, AdjCtx &C, const void *u_host, void *lam_host,
   return SO2DR_OK;
 }
 
-int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, double *grad_w,
-                double *loss, int ckpt_every, void *const *ckpt, int n_ckpt, so2dr_stats *st) {
+static int adjoint_impl(Plan &P, const void *u0, const void *target, void *grad_u0, double *grad_w,
+                        double *loss, int ckpt_every, void *const *ckpt, int n_ckpt, so2dr_stats *st) {
   if (!P.bound) {
     set_error("plan is not bound to device memory and streams");
     return SO2DR_E_UNBOUND;
@@ -388,6 +388,15 @@ int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, doub
   S.rounds_done = nseg;
   if (st) *st = S;
   return SO2DR_OK;
+}
+
+// On a failure part-way the work already queued is drained before
+// returning, so the caller may release the arena and host buffers at once.
+int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, double *grad_w,
+                double *loss, int ckpt_every, void *const *ckpt, int n_ckpt, so2dr_stats *st) {
+  const int rc = adjoint_impl(P, u0, target, grad_u0, grad_w, loss, ckpt_every, ckpt, n_ckpt, st);
+  if (rc && P.bound) drain_streams(P);
+  return rc;
 }
 
 }  // namespace so2dr

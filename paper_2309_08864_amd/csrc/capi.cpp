@@ -21,6 +21,8 @@ int adjoint_run(Plan &P, const void *u0, const void *target, void *grad_u0, doub
 void default_machine(const Plan &P, so2dr_machine *m);
 double predict_seconds(const Plan &P, const so2dr_machine &m, int steps);
 int suggest(const so2dr_desc &in, const so2dr_machine *mp, so2dr_desc *out, double *pred_ms);
+int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t in_planes, int reps,
+                 hipStream_t s, double *ms);
 }  // namespace so2dr
 
 using so2dr::set_error;
@@ -134,6 +136,29 @@ int so2dr_plan_get_ops(const so2dr_plan *plan, so2dr_op *ops, int64_t n) {
   GUARD_END
 }
 
+int so2dr_plan_get_deps(const so2dr_plan *plan, int n_streams, int32_t *stream, int64_t *waits,
+                        int64_t n) {
+  GUARD_BEGIN
+  if (!plan || n < 0 || (n > 0 && (!stream || !waits)) || n_streams < 1) {
+    set_error("null plan or output, negative n, or no stream");
+    return SO2DR_E_INVALID;
+  }
+  auto all = so2dr::build_ops(plan->p, plan->p.T, nullptr);
+  if (n > (int64_t)all.size()) {
+    set_error("n exceeds the schedule length");
+    return SO2DR_E_INVALID;
+  }
+  std::vector<int> strm;
+  std::vector<int64_t> w;
+  so2dr::schedule_deps(plan->p, all, n_streams, &strm, &w);
+  for (int64_t k = 0; k < n; ++k) {
+    stream[k] = strm[(size_t)k];
+    for (int i = 0; i < SO2DR_MAX_WAITS; ++i) waits[k * SO2DR_MAX_WAITS + i] = w[(size_t)k * so2dr::kMaxWaits + i];
+  }
+  return SO2DR_OK;
+  GUARD_END
+}
+
 int so2dr_machine_default(const so2dr_plan *plan, so2dr_machine *m) {
   GUARD_BEGIN
   if (!plan || !m) {
@@ -225,6 +250,18 @@ int so2dr_adjoint_run(so2dr_plan *plan, const void *host_u0, const void *host_ta
   }
   return so2dr::adjoint_run(plan->p, host_u0, host_target, host_grad_u0, grad_w, loss,
                             ckpt_every, host_ckpt, n_ckpt, st);
+  GUARD_END
+}
+
+int so2dr_kernel_bench(const so2dr_plan *plan, int levels, void *dev_in, void *dev_out,
+                       int64_t in_planes, int reps, void *stream, double *ms) {
+  GUARD_BEGIN
+  if (!plan) {
+    set_error("null plan");
+    return SO2DR_E_INVALID;
+  }
+  return so2dr::kernel_bench(plan->p, levels, dev_in, dev_out, in_planes, reps,
+                             static_cast<hipStream_t>(stream), ms);
   GUARD_END
 }
 

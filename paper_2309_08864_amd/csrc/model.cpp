@@ -3,9 +3,10 @@
 // and fused steps that the paper leaves to future work, Sec. IV-C / VII).
 //
 // The model replays the plan's own schedule (build_ops) through the
-// executor's dependency rules -- copy-in and copy-out streams in order, one
-// compute stream, slot reuse, region-sharing order, host hazards between
-// rounds -- with each operation's duration taken from machine figures: host
+// executor's dependency rules (schedule_deps, the code the executor runs:
+// copy-in and copy-out streams in order, one compute stream, slot reuse,
+// region-sharing order, host hazards between rounds) with each operation's
+// duration taken from machine figures: host
 // link rates (solo and full duplex), device copy rate, fixed launch cost and
 // the measured update rate of a fused launch per depth.
 #include <algorithm>
@@ -67,8 +68,11 @@ namespace {
 double simulate(const Plan &P, const so2dr_machine &m, int steps) {
   int64_t computed = 0;
   const std::vector<so2dr_op> ops = build_ops(P, steps, &computed);
-  const int nt = n_rounds_for(P, steps);
-  const size_t nseq = (size_t)std::max(nt, 1) * P.d;
+  // the executor's own stream assignment and waits, for the library's
+  // three streams (copy-in, copy-out, compute)
+  std::vector<int> strm;
+  std::vector<int64_t> waits;
+  schedule_deps(P, ops, 3, &strm, &waits);
   // with two or more slots both copy directions run together most of the time
   const bool duplex = P.n_slots >= 2;
   double both = m.duplex_gbps;
@@ -80,55 +84,31 @@ double simulate(const Plan &P, const so2dr_machine &m, int steps) {
   S.bw_d2d = 1e9 * m.d2d_gbps;
   S.launch_s = 1e-6 * m.launch_us;
   const size_t pb = P.plane_bytes();
-  std::vector<double> end_h2d(nseq, 0.0), end_d2h(nseq, 0.0), end_comp(nseq, 0.0);
-  std::map<int64_t, double> rs_last;
-  double t_in = 0, t_out = 0, t_comp = 0, t_end = 0;
-  int comp_g = -1;
-  for (const so2dr_op &op : ops) {
-    const size_t g = (size_t)op.round * P.d + op.chunk;
+  std::vector<double> end(ops.size(), 0.0);
+  double stream_end[3] = {0.0, 0.0, 0.0}, t_end = 0.0;
+  for (size_t k = 0; k < ops.size(); ++k) {
+    const so2dr_op &op = ops[k];
     const double bytes = (double)(op.z1 - op.z0) * (double)pb;
-    double start = 0, dur = 0;
+    double start = stream_end[strm[k]];
+    for (int i = 0; i < kMaxWaits; ++i) {
+      const int64_t w = waits[k * kMaxWaits + i];
+      if (w >= 0) start = std::max(start, end[(size_t)w]);
+    }
+    double dur = 0.0;
     switch (op.kind) {
-      case SO2DR_OP_H2D:
-        start = t_in;
-        if ((int)g >= P.n_slots) start = std::max(start, end_d2h[g - P.n_slots]);
-        if (op.round > 0) {
-          start = std::max(start, end_d2h[g - P.d]);
-          if (op.chunk + 1 < P.d) start = std::max(start, end_d2h[g - P.d + 1]);
-        }
-        dur = bytes / S.bw_in;
-        t_in = end_h2d[g] = start + dur;
-        break;
-      case SO2DR_OP_RS_READ:
-      case SO2DR_OP_RS_WRITE:
+      case SO2DR_OP_H2D: dur = bytes / S.bw_in; break;
+      case SO2DR_OP_D2H: dur = bytes / S.bw_out; break;
       case SO2DR_OP_KERNEL: {
-        start = t_comp;
-        if (comp_g != (int)g) {
-          start = std::max(start, end_h2d[g]);
-          comp_g = (int)g;
-        }
-        if (op.kind == SO2DR_OP_KERNEL) {
-          const double rate = op.levels >= 1 && op.levels <= 8 ? m.gupd[op.levels - 1] : 0.0;
-          const double upd = (double)(op.z1 - op.z0) * (double)P.plane * op.levels;
-          dur = S.launch_s + (rate > 0 ? upd / (rate * 1e9) : 1e30);
-        } else {
-          auto it = rs_last.find(op.pool_off);
-          if (it != rs_last.end()) start = std::max(start, it->second);
-          dur = 2.0 * bytes / S.bw_d2d + S.launch_s;
-        }
-        t_comp = end_comp[g] = start + dur;
-        if (op.kind != SO2DR_OP_KERNEL) rs_last[op.pool_off] = t_comp;
+        const double rate = op.levels >= 1 && op.levels <= 8 ? m.gupd[op.levels - 1] : 0.0;
+        const double upd = (double)(op.z1 - op.z0) * (double)P.plane * op.levels;
+        dur = S.launch_s + (rate > 0 ? upd / (rate * 1e9) : 1e30);
         break;
       }
-      case SO2DR_OP_D2H:
-        start = std::max(t_out, end_comp[g]);
-        dur = bytes / S.bw_out;
-        t_out = end_d2h[g] = start + dur;
-        break;
-      default:
-        break;
+      default: dur = 2.0 * bytes / S.bw_d2d + S.launch_s; break;   // region-sharing copies
     }
-    t_end = std::max(t_end, start + dur);
+    end[k] = start + dur;
+    stream_end[strm[k]] = end[k];
+    t_end = std::max(t_end, end[k]);
   }
   return t_end;
 }

@@ -43,7 +43,8 @@ struct Plan {
   std::vector<hipStream_t> streams;
   bool bound = false;
   bool timing = false;
-  std::vector<hipEvent_t> ev_rs, ev_d2h, ev_h2d, ev_comp;   // indexed by round * d + chunk
+  std::vector<hipEvent_t> ev_rs, ev_d2h, ev_h2d, ev_comp;   // adjoint sweep: round * d + chunk
+  std::vector<hipEvent_t> ev_op;           // forward runs: completion of op k (when awaited)
   std::vector<hipEvent_t> ev_t;            // timing pairs, 2 per op
   ~Plan();
 
@@ -70,6 +71,13 @@ int n_rounds_for(const Plan &P, int steps);
 int64_t area_lo(const Plan &P, int i, int kp, int s);
 int64_t area_hi(const Plan &P, int i, int kp, int s);
 
+// The executor's dependency rules for a schedule run on n_streams streams:
+// the stream index of every op and the (at most kMaxWaits) earlier ops whose
+// completion it waits for, -1 padded.  Ops on one stream run in list order.
+constexpr int kMaxWaits = SO2DR_MAX_WAITS;
+void schedule_deps(const Plan &P, const std::vector<so2dr_op> &ops, int n_streams,
+                   std::vector<int> *stream, std::vector<int64_t> *waits);
+
 // Build the schedule for `steps` steps (Algorithm 1 unrolled).  Also returns
 // the number of cell-plane updates computed (including redundant ones).
 std::vector<so2dr_op> build_ops(const Plan &P, int steps, int64_t *planes_computed);
@@ -88,6 +96,10 @@ constexpr size_t kKernelCopyBelow = (size_t)512 << 20;
 constexpr int64_t kKernelCopyQueued = 256;
 // Workgroups of one host-copy kernel (about the link's rate per direction).
 constexpr int kHostCopyWgs = 64;
+
+// Wait for whatever a failed run already queued on the plan's streams
+// (errors ignored; the caller reports the first one).
+void drain_streams(Plan &P);
 
 // Device address of the host range [p, p + bytes) when it lies inside one
 // page-locked allocation mapped into the current device, else null.

@@ -25,6 +25,7 @@
 //     planes below its own range) follows chunk i-1's copy-in through the
 //     region-sharing chain.
 // Nothing synchronises the device between rounds.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -36,6 +37,7 @@
 namespace so2dr {
 
 Plan::~Plan() {
+  for (auto e : ev_op) hipEventDestroy(e);
   for (auto e : ev_rs) hipEventDestroy(e);
   for (auto e : ev_d2h) hipEventDestroy(e);
   for (auto e : ev_h2d) hipEventDestroy(e);
@@ -59,6 +61,11 @@ static int ensure_events(std::vector<hipEvent_t> &v, size_t n, unsigned flags) {
     v.push_back(e);
   }
   return SO2DR_OK;
+}
+
+void drain_streams(Plan &P) {
+  for (hipStream_t s : P.streams) (void)hipStreamSynchronize(s);
+  (void)hipGetLastError();
 }
 
 int check_pinned(const void *p, size_t bytes, const char *what) {
@@ -170,6 +177,71 @@ int bind_plan(Plan &P, void *arena, size_t bytes, void *const *streams, int n_st
   return SO2DR_OK;
 }
 
+void schedule_deps(const Plan &P, const std::vector<so2dr_op> &ops, int ns, std::vector<int> *stream,
+                   std::vector<int64_t> *waits) {
+  const size_t n = ops.size();
+  stream->assign(n, 0);
+  waits->assign(n * kMaxWaits, -1);
+  const int nc = ns >= 3 ? ns - 2 : 1;
+  int64_t n_seq = 0;
+  for (const so2dr_op &op : ops) n_seq = std::max<int64_t>(n_seq, (int64_t)op.round * P.d + op.chunk + 1);
+  std::vector<int64_t> h2d_of(n_seq, -1), d2h_of(n_seq, -1);
+  std::map<int64_t, int64_t> last_rs;   // region-sharing slot -> its last access
+  int64_t comp_g = -1;
+  for (size_t k = 0; k < n; ++k) {
+    const so2dr_op &op = ops[k];
+    const int64_t g = (int64_t)op.round * P.d + op.chunk;
+    int64_t *w = waits->data() + k * kMaxWaits;
+    int nw = 0;
+    switch (op.kind) {
+      case SO2DR_OP_H2D:
+        (*stream)[k] = 0;
+        // slot reuse: the copy-out of the chunk that held this slot before
+        if (g >= P.n_slots) w[nw++] = d2h_of[g - P.n_slots];
+        // host array in place: last round's copy-outs of chunks i and i+1
+        // write the planes this copy-in reads
+        if (op.round > 0) {
+          w[nw++] = d2h_of[g - P.d];
+          if (op.chunk + 1 < P.d) w[nw++] = d2h_of[g - P.d + 1];
+        }
+        h2d_of[g] = (int64_t)k;
+        break;
+      case SO2DR_OP_RS_READ:
+      case SO2DR_OP_RS_WRITE:
+      case SO2DR_OP_KERNEL: {
+        (*stream)[k] = ns >= 3 ? 2 + (int)(g % nc) : 0;
+        if (comp_g != g) {   // first compute op of the chunk: its input is in HBM
+          w[nw++] = h2d_of[g];
+          comp_g = g;
+        }
+        if (op.kind != SO2DR_OP_KERNEL) {   // read, then write, in schedule order
+          auto it = last_rs.find(op.pool_off);
+          if (it != last_rs.end()) w[nw++] = it->second;
+          last_rs[op.pool_off] = (int64_t)k;
+        }
+        break;
+      }
+      case SO2DR_OP_D2H:
+        (*stream)[k] = ns >= 2 ? 1 : 0;
+        w[nw++] = (int64_t)k - 1;   // the chunk's last compute op
+        d2h_of[g] = (int64_t)k;
+        break;
+      default:
+        break;
+    }
+    // drop waits on ops of the same stream (list order covers them) and on
+    // nothing (-1), and duplicates
+    int m = 0;
+    for (int i = 0; i < nw; ++i) {
+      const int64_t x = w[i];
+      bool keep = x >= 0 && (*stream)[x] != (*stream)[k];
+      for (int j = 0; j < m && keep; ++j) keep = w[j] != x;
+      if (keep) w[m++] = x;
+    }
+    for (int i = m; i < kMaxWaits; ++i) w[i] = -1;
+  }
+}
+
 // Run `steps` steps from host_in into host_out (may alias).
 int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats *st) {
   if (!P.bound) {
@@ -210,69 +282,35 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
   }
   int64_t computed = 0;
   const std::vector<so2dr_op> ops = build_ops(P, steps, &computed);
-  const int nt = n_rounds_for(P, steps);
-  const size_t nseq = (size_t)nt * P.d;
-  rc = ensure_events(P.ev_rs, nseq, hipEventDisableTiming);
-  if (rc) return rc;
-  rc = ensure_events(P.ev_d2h, nseq, hipEventDisableTiming);
+  const int ns = (int)P.streams.size();
+  std::vector<int> strm;
+  std::vector<int64_t> waits;
+  schedule_deps(P, ops, ns, &strm, &waits);
+  // an event after every op that a later op on another stream waits for
+  std::vector<char> awaited(ops.size(), 0);
+  for (int64_t x : waits)
+    if (x >= 0) awaited[(size_t)x] = 1;
+  rc = ensure_events(P.ev_op, ops.size(), hipEventDisableTiming);
   if (rc) return rc;
   if (P.timing) {
     rc = ensure_events(P.ev_t, 2 * ops.size(), hipEventDefault);
     if (rc) return rc;
   }
-  rc = ensure_events(P.ev_h2d, nseq, hipEventDisableTiming);
-  if (rc) return rc;
-  rc = ensure_events(P.ev_comp, nseq, hipEventDisableTiming);
-  if (rc) return rc;
   const size_t pb = P.plane_bytes();
   const char *hin = static_cast<const char *>(host_in);
   char *hout = static_cast<char *>(host_out);
-  const int ns = (int)P.streams.size();
-  hipStream_t s_in = P.streams[0];
-  hipStream_t s_out = ns >= 2 ? P.streams[1] : P.streams[0];
-  const int nc = ns >= 3 ? ns - 2 : 1;
-  auto s_comp = [&](int g) { return ns >= 3 ? P.streams[2 + g % nc] : P.streams[0]; };
   std::string msg;
-  // region-sharing buffer: every access to a pool slot waits for the previous
-  // access to that slot (write -> read -> write ... in schedule order)
-  size_t n_rs = 0;
-  for (const so2dr_op &op : ops) n_rs += (op.kind == SO2DR_OP_RS_READ || op.kind == SO2DR_OP_RS_WRITE);
-  rc = ensure_events(P.ev_rs, n_rs, hipEventDisableTiming);
-  if (rc) return rc;
-  std::map<int64_t, size_t> last_on_slot;
-  size_t rs_k = 0;
-  int comp_g = -1;   // sequence index of the chunk whose compute ops are being enqueued
+  // every operation is enqueued here; on a failure part-way, the work
+  // already queued is drained before returning (so the caller may release
+  // the arena at once)
+  auto enqueue = [&]() -> int {
   for (size_t k = 0; k < ops.size(); ++k) {
     const so2dr_op &op = ops[k];
-    const int g = op.round * P.d + op.chunk;
-    const bool is_rs = op.kind == SO2DR_OP_RS_READ || op.kind == SO2DR_OP_RS_WRITE;
-    hipStream_t s = op.kind == SO2DR_OP_H2D ? s_in : op.kind == SO2DR_OP_D2H ? s_out : s_comp(g);
+    hipStream_t s = P.streams[strm[k]];
     // cross-stream waits, enqueued before the op's timing start
-    switch (op.kind) {
-      case SO2DR_OP_H2D:
-        if (g >= P.n_slots) HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.n_slots], 0));
-        if (op.round > 0) {
-          HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.d], 0));
-          if (op.chunk + 1 < P.d) HIPCHK(hipStreamWaitEvent(s, P.ev_d2h[g - P.d + 1], 0));
-        }
-        break;
-      case SO2DR_OP_RS_READ:
-      case SO2DR_OP_RS_WRITE:
-      case SO2DR_OP_KERNEL:
-        if (comp_g != g) {  // first compute op of this chunk: its input is in HBM
-          HIPCHK(hipStreamWaitEvent(s, P.ev_h2d[g], 0));
-          comp_g = g;
-        }
-        if (is_rs) {
-          auto it = last_on_slot.find(op.pool_off);
-          if (it != last_on_slot.end()) HIPCHK(hipStreamWaitEvent(s, P.ev_rs[it->second], 0));
-        }
-        break;
-      case SO2DR_OP_D2H:
-        HIPCHK(hipStreamWaitEvent(s, P.ev_comp[g], 0));
-        break;
-      default:
-        break;
+    for (int i = 0; i < kMaxWaits; ++i) {
+      const int64_t x = waits[k * kMaxWaits + i];
+      if (x >= 0) HIPCHK(hipStreamWaitEvent(s, P.ev_op[(size_t)x], 0));
     }
     if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k], s));
     switch (op.kind) {
@@ -303,8 +341,6 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
           set_error("region-sharing copy kernel launch failed");
           return SO2DR_E_HIP;
         }
-        HIPCHK(hipEventRecord(P.ev_rs[rs_k], s));
-        last_on_slot[op.pool_off] = rs_k++;
         S.bytes_d2d += n;
         break;
       }
@@ -334,8 +370,13 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
           set_error(msg);
           return rc;
         }
+        const uint64_t alg = (uint64_t)((op.in_z1 - op.in_z0) + (op.z1 - op.z0)) * pb;
         S.kernel_launches += 1;
-        S.kernel_alg_bytes += (uint64_t)((op.in_z1 - op.in_z0) + (op.z1 - op.z0)) * pb;
+        S.kernel_alg_bytes += alg;
+        if (op.levels >= 1 && op.levels <= 8) {
+          S.launches_by_levels[op.levels - 1] += 1;
+          S.alg_bytes_by_levels[op.levels - 1] += alg;
+        }
         break;
       }
       case SO2DR_OP_D2H: {
@@ -351,11 +392,14 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
         return SO2DR_E_INVALID;
     }
     if (P.timing) HIPCHK(hipEventRecord(P.ev_t[2 * k + 1], s));
-    // completion events other streams wait on
-    if (op.kind == SO2DR_OP_H2D) HIPCHK(hipEventRecord(P.ev_h2d[g], s));
-    if (op.kind == SO2DR_OP_D2H) HIPCHK(hipEventRecord(P.ev_d2h[g], s));
-    // the op before a copy-out is the chunk's last compute op
-    if (k + 1 < ops.size() && ops[k + 1].kind == SO2DR_OP_D2H) HIPCHK(hipEventRecord(P.ev_comp[g], s));
+    if (awaited[k]) HIPCHK(hipEventRecord(P.ev_op[k], s));
+  }
+  return SO2DR_OK;
+  };
+  rc = enqueue();
+  if (rc) {
+    drain_streams(P);
+    return rc;
   }
   for (hipStream_t s : P.streams) HIPCHK(hipStreamSynchronize(s));
   const auto t_end = std::chrono::steady_clock::now();
@@ -369,12 +413,88 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
       switch (ops[k].kind) {
         case SO2DR_OP_H2D: S.h2d_ms += ms; break;
         case SO2DR_OP_D2H: S.d2h_ms += ms; break;
-        case SO2DR_OP_KERNEL: S.kernel_ms += ms; break;
+        case SO2DR_OP_KERNEL:
+          S.kernel_ms += ms;
+          if (ops[k].levels >= 1 && ops[k].levels <= 8) S.kernel_ms_by_levels[ops[k].levels - 1] += ms;
+          break;
         default: S.d2d_ms += ms; break;
       }
     }
   }
   if (st) *st = S;
+  return SO2DR_OK;
+}
+
+int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t in_planes, int reps,
+                 hipStream_t s, double *ms) {
+  if (!dev_in || !dev_out || !ms || reps < 1 || levels < 0 || levels > P.max_k_on) {
+    set_error("null buffer or output, reps < 1, or levels outside [0, max_k_on]");
+    return SO2DR_E_INVALID;
+  }
+  const int64_t halo = (int64_t)levels * P.r;
+  if (in_planes <= 2 * halo || in_planes > P.N) {
+    set_error("in_planes must exceed 2 * levels * radius and not exceed the cut axis");
+    return SO2DR_E_INVALID;
+  }
+  const size_t pb = P.plane_bytes();
+  // the planes sit in the middle of the cut axis: an interior chunk
+  const int64_t base = (P.N - in_planes) / 2;
+  LaunchParams lp;
+  lp.stencil = P.stencil;
+  lp.kl = levels;
+  lp.in = dev_in;
+  lp.out = dev_out;
+  lp.buf_z0 = base;
+  lp.out_z0 = base;
+  lp.plane = P.plane;
+  lp.nx = (int)P.NX;
+  lp.ny = (int)P.NY;
+  lp.per_x = P.per_x;
+  lp.per_y = P.per_y;
+  lp.n_axis = P.N;
+  lp.in_lo = base;
+  lp.in_hi = base + in_planes;
+  lp.out_lo = base + halo;
+  lp.out_hi = base + in_planes - halo;
+  lp.weights = P.weights.data();
+  lp.npts = (int)P.weights.size();
+  lp.ras = P.ras;
+  std::string msg;
+  auto launch = [&]() -> int {
+    if (levels == 0) {
+      if (launch_dcopy(dev_out, dev_in, (size_t)in_planes * pb, s)) {
+        set_error("copy kernel launch failed");
+        return SO2DR_E_HIP;
+      }
+      return SO2DR_OK;
+    }
+    const int rc = launch_tb(P.dtype, lp, s, &msg);
+    if (rc) set_error(msg);
+    return rc;
+  };
+  int rc = launch();   // first launch: one-time set-up outside the timing
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return SO2DR_E_HIP;
+  }
+  hipError_t e = hipEventRecord(e0, s);
+  for (int i = 0; i < reps && e == hipSuccess && rc == SO2DR_OK; ++i) rc = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess && rc == SO2DR_OK) e = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if (e != hipSuccess) {
+    set_error(std::string("kernel timing: ") + hipGetErrorString(e));
+    return SO2DR_E_HIP;
+  }
+  *ms = (double)t / reps;
   return SO2DR_OK;
 }
 

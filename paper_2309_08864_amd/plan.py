@@ -76,6 +76,17 @@ class Plan:
             out.append(d)
         return out
 
+    def deps(self, n_streams=3):
+        """The executor's schedule on n_streams streams: (stream index per op,
+        list of earlier ops each op waits for), as so2dr_plan_get_deps."""
+        n = self.info()["n_ops"]
+        strm = (ctypes.c_int32 * max(n, 1))()
+        w = (ctypes.c_int64 * max(n * _lib.MAX_WAITS, 1))()
+        check(lib().so2dr_plan_get_deps(self._h, int(n_streams), strm, w, n))
+        waits = [[x for x in w[k * _lib.MAX_WAITS:(k + 1) * _lib.MAX_WAITS] if x >= 0]
+                 for k in range(n)]
+        return list(strm[:n]), waits
+
     def machine(self):
         """The built-in machine figures for this plan's stencil and storage."""
         m = _lib.Machine()
@@ -101,6 +112,23 @@ class Plan:
         check(lib().so2dr_plan_bind(self._h, ctypes.c_void_p(self._arena.data_ptr()),
                                     self._arena.numel(), arr, ns))
         return self
+
+    def kernel_ms(self, levels, in_planes, reps=20, device="cuda"):
+        """Mean time (ms) of one launch of this plan's kernel fusing `levels`
+        steps over an interior chunk of `in_planes` planes (levels = 0: the
+        library's device copy kernel over those planes), on device buffers
+        allocated here (so2dr_kernel_bench)."""
+        import torch
+        esz = torch.empty((), dtype=getattr(torch, TORCH_DTYPES[self.storage])).element_size()
+        n = int(in_planes) * int(self.info()["plane_elems"]) * esz
+        src = torch.rand((n + 3) // 4, dtype=torch.float32, device=device)   # timing only
+        dst = torch.zeros_like(src)
+        s = _plan_streams(device, 3)[2]
+        ms = ctypes.c_double()
+        check(lib().so2dr_kernel_bench(self._h, int(levels), ctypes.c_void_p(src.data_ptr()),
+                                       ctypes.c_void_p(dst.data_ptr()), int(in_planes), int(reps),
+                                       ctypes.c_void_p(s.cuda_stream), ctypes.byref(ms)))
+        return ms.value
 
     def set_timing(self, enable=True):
         check(lib().so2dr_plan_set_timing(self._h, 1 if enable else 0))
