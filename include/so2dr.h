@@ -246,6 +246,29 @@ int so2dr_plan_set_timing(struct so2dr_plan *plan, int enable);
  * st->rounds_done tells how many rounds completed). */
 int so2dr_run(struct so2dr_plan *plan, void *host_u, so2dr_stats *st);
 
+/* Bytes of the static device workspace so2dr_run_noalloc runs in. */
+#define SO2DR_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+
+/* so2dr_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same executor and kernels, but the plan's workspace (slot buffers and the
+ * region-sharing buffer) is a static device array of the library,
+ * SO2DR_NOALLOC_MAX_BYTES bytes per GPU, held from the first call on a
+ * device until the process ends; no hipMalloc, hipFree or other allocating
+ * routine is called (the plan's HIP events are created on first use, as by
+ * so2dr_run).  host_u: as for so2dr_run (pinned, u_0 in, u_T out, in place).
+ * streams / n_streams: as for so2dr_plan_bind, on the current device, used
+ * for this call only.  The plan need not be bound; a binding it has is left
+ * as it was.  Nothing in the workspace has to start at zero: every byte a
+ * kernel reads is written earlier in the same call.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap in time on one GPU race
+ * (each returns only when its work is done, so calls from one thread never
+ * overlap).  Errors: E_BUDGET (the plan's workspace exceeds
+ * SO2DR_NOALLOC_MAX_BYTES), E_INVALID (null plan or stream), E_NOT_PINNED,
+ * E_HIP (also when the array's device address cannot be obtained). */
+int so2dr_run_noalloc(struct so2dr_plan *plan, void *host_u, void *const *streams, int n_streams,
+                      so2dr_stats *st);
+
 /* As so2dr_run but out of place and for `steps` steps (0 < steps <= T, same
  * chunking and depth): host_in is read-only, host_out receives u_steps.
  * host_in == host_out is the in-place run. */

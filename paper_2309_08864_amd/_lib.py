@@ -23,11 +23,13 @@ EXPORTS = ["so2dr_plan_create", "so2dr_plan_destroy", "so2dr_plan_get_info",
            "so2dr_plan_workspace_bytes", "so2dr_plan_get_ops", "so2dr_plan_bind",
            "so2dr_plan_set_timing", "so2dr_run", "so2dr_run_steps", "so2dr_adjoint_run",
            "so2dr_last_error", "so2dr_version", "so2dr_machine_default", "so2dr_plan_predict",
-           "so2dr_plan_suggest", "so2dr_host_alloc", "so2dr_host_free",
+           "so2dr_plan_suggest", "so2dr_host_alloc", "so2dr_host_free", "so2dr_run_noalloc",
            "so2dr_plan_get_deps", "so2dr_kernel_bench"]
 
 MAX_WAITS = 4   # SO2DR_MAX_WAITS
 
+# SO2DR_NOALLOC_MAX_BYTES: the static device workspace of so2dr_run_noalloc.
+NOALLOC_MAX_BYTES = 128 << 20
 
 
 class Desc(ctypes.Structure):
@@ -110,6 +112,7 @@ def lib():
         L.so2dr_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp), i32]
         L.so2dr_plan_set_timing.argtypes = [vp, i32]
         L.so2dr_run.argtypes = [vp, vp, ctypes.POINTER(Stats)]
+        L.so2dr_run_noalloc.argtypes = [vp, vp, ctypes.POINTER(vp), i32, ctypes.POINTER(Stats)]
         L.so2dr_run_steps.argtypes = [vp, vp, vp, i32, ctypes.POINTER(Stats)]
         L.so2dr_adjoint_run.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(vp),
@@ -127,7 +130,7 @@ def lib():
                   "so2dr_plan_get_ops", "so2dr_plan_bind", "so2dr_plan_set_timing", "so2dr_run",
                   "so2dr_run_steps", "so2dr_adjoint_run", "so2dr_machine_default",
                   "so2dr_plan_predict", "so2dr_plan_suggest", "so2dr_host_alloc",
-                  "so2dr_host_free", "so2dr_plan_get_deps",
+                  "so2dr_host_free", "so2dr_run_noalloc", "so2dr_plan_get_deps",
                   "so2dr_kernel_bench"):
             getattr(L, f).restype = i32
         _LIB = L

@@ -2,6 +2,7 @@
 // arguments, catches every C++ exception and reports failures through a
 // return code plus a thread-local message.
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -26,6 +27,40 @@ int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t
 }  // namespace so2dr
 
 using so2dr::set_error;
+
+// Device workspace of so2dr_run_noalloc: one array per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address comes from hipGetSymbolAddress, asked
+// once per device (with that device current) and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[SO2DR_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch`, or null with the error set.
+void *scratch_on_current_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error(std::string("hipGetDevice: ") + (e != hipSuccess ? hipGetErrorString(e) : "device index out of range"));
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") +
+                (e != hipSuccess ? hipGetErrorString(e) : "null address"));
+      return nullptr;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+}  // namespace
 
 #define GUARD_BEGIN try {
 #define GUARD_END                                            \
@@ -222,6 +257,51 @@ int so2dr_run(so2dr_plan *plan, void *host_u, so2dr_stats *st) {
     return SO2DR_E_INVALID;
   }
   return so2dr::execute(plan->p, host_u, host_u, plan->p.T, st);
+  GUARD_END
+}
+
+int so2dr_run_noalloc(so2dr_plan *plan, void *host_u, void *const *streams, int n_streams,
+                      so2dr_stats *st) {
+  GUARD_BEGIN
+  if (!plan) {
+    set_error("null plan");
+    return SO2DR_E_INVALID;
+  }
+  so2dr::Plan &P = plan->p;
+  if (P.workspace > SO2DR_NOALLOC_MAX_BYTES) {
+    set_error("plan workspace of " + std::to_string(P.workspace) +
+              " bytes exceeds the static workspace of so2dr_run_noalloc (" +
+              std::to_string((size_t)SO2DR_NOALLOC_MAX_BYTES) + " bytes)");
+    return SO2DR_E_BUDGET;
+  }
+  if (!streams || n_streams < 1) {
+    set_error("at least one stream is needed");
+    return SO2DR_E_INVALID;
+  }
+  for (int i = 0; i < n_streams; ++i)
+    if (!streams[i]) {
+      set_error("null stream");
+      return SO2DR_E_INVALID;
+    }
+  char *ws = static_cast<char *>(scratch_on_current_device());
+  if (!ws) return SO2DR_E_HIP;
+  // run on the static workspace, then give the plan back whatever binding
+  // it had (so2dr_run keeps working on the caller's arena)
+  char *old_arena = P.arena;
+  const size_t old_bytes = P.arena_bytes;
+  std::vector<hipStream_t> old_streams = P.streams;
+  const bool old_bound = P.bound;
+  P.arena = ws;
+  P.arena_bytes = SO2DR_NOALLOC_MAX_BYTES;
+  P.streams.clear();
+  for (int i = 0; i < n_streams; ++i) P.streams.push_back(static_cast<hipStream_t>(streams[i]));
+  P.bound = true;
+  const int rc = so2dr::execute(P, host_u, host_u, P.T, st);
+  P.arena = old_arena;
+  P.arena_bytes = old_bytes;
+  P.streams.swap(old_streams);
+  P.bound = old_bound;
+  return rc;
   GUARD_END
 }
 

@@ -140,6 +140,18 @@ class Plan:
         check(lib().so2dr_run(self._h, ctypes.c_void_p(host_u.data_ptr()), ctypes.byref(st)))
         return st.as_dict()
 
+    def run_noalloc(self, host_u, device="cuda", n_streams=3):
+        """As run(), in the library's static device workspace
+        (so2dr_run_noalloc): no device memory is allocated for the call, and
+        the plan need not be bound."""
+        self._check_host(host_u)
+        streams = _plan_streams(device, n_streams)
+        arr = (ctypes.c_void_p * n_streams)(*[s.cuda_stream for s in streams])
+        st = _lib.Stats()
+        check(lib().so2dr_run_noalloc(self._h, ctypes.c_void_p(host_u.data_ptr()), arr, n_streams,
+                                      ctypes.byref(st)))
+        return st.as_dict()
+
     def run_steps(self, host_in, host_out, steps):
         self._check_host(host_in)
         self._check_host(host_out)
