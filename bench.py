@@ -111,6 +111,8 @@ def parse():
                     help="instead of a run: time one launch per fused depth and storage type of "
                          "the workload's stencil on an interior chunk (so2dr_kernel_bench) and "
                          "print one JSON line per kernel")
+    ap.add_argument("--grid", default=None,
+                    help="with --kernel-rates: override the workload's extents, NXxNY or NXxNYxNZ")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of one run: the workload under every chunk count x TB depth "
                          "of --sweep-chunks / --sweep-depths, one JSON line each")
@@ -468,11 +470,14 @@ def kernel_rates(args, wl, offs, w):
     device copy kernel over the same planes."""
     import workloads
     from paper_2309_08864_amd import So2drError
+    from paper_2309_08864_amd import Plan
     storages = [args.storage] if args.storage else ["f32", "bf16", "f16", "f64"]
     for storage in storages:
         ww = w if storage == "f64" else workloads.fp32_rounded(w)
         try:
-            p = plan_for(wl, ww, storage, args, wl.tb_depth, wl.n_chunks or 1)
+            p = Plan(ndim=wl.ndim, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape=wl.shape, radius=wl.radius,
+                     weights=list(ww), T=wl.T, tb_depth=wl.T, n_chunks=1, budget=1 << 40,
+                     storage=storage, bc=wl.periodic)
         except So2drError as e:
             print(json.dumps({"storage": storage, "error": str(e)}), flush=True)
             continue
@@ -485,7 +490,8 @@ def kernel_rates(args, wl, offs, w):
             ms = p.kernel_ms(L, in_planes, reps=20)
             out_planes = own if L else in_planes
             alg = (in_planes + out_planes) * pb
-            line = {"workload": wl.name, "storage": storage, "levels": L,
+            line = {"workload": wl.name, "grid": f"{wl.nx}x{wl.ny}x{wl.nz}", "storage": storage,
+                    "levels": L,
                     "kernel": "device copy" if L == 0 else "fused stencil",
                     "in_planes": in_planes, "plane_bytes": pb, "ms": round(ms, 4),
                     "alg_GBps": round(alg / ms / 1e6, 1),
@@ -606,6 +612,10 @@ def main():
     if args.T:
         import dataclasses
         wl = dataclasses.replace(wl, T=args.T)
+    if args.grid:
+        import dataclasses
+        ext = [int(x) for x in args.grid.lower().split("x")]
+        wl = dataclasses.replace(wl, nx=ext[0], ny=ext[1], nz=ext[2] if len(ext) > 2 else 1)
     storage = args.storage or wl.dtypes[0]
     offs = stencil_offsets(wl.ndim, wl.shape, wl.radius)
     w = weights_for(wl, offs)

@@ -115,7 +115,7 @@ typedef struct {
   int n_chunks;               /* d; 0 = choose the fewest that fit the budget */
   int tb_depth;               /* K = S_TB: steps per HBM residency; 0 = T */
   int k_on;                   /* steps fused per kernel launch; 0 = automatic */
-  int n_slots;                /* in-flight chunks (= streams); 0 = automatic, at most 3 */
+  int n_slots;                /* chunks in flight (slot buffers): 0 = automatic (at most 3), else 1..4 */
   size_t device_budget_bytes; /* hard cap on the device memory the plan may use */
   int adjoint;                /* 1: also reserve what so2dr_adjoint_run needs */
   int method;                 /* so2dr_method: SO2DR_METHOD_SO2DR (default) or _RESREU */

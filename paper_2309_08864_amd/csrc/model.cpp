@@ -16,27 +16,13 @@
 #include <vector>
 
 #include "plan.hpp"
+#include "rates.hpp"
 
 namespace so2dr {
 
 int max_depth(int dtype, int stencil);
 
 namespace {
-
-// G cell-updates/s (output cells x fused levels per second) of one launch
-// over a large chunk, FP32 storage, on MI355X, by stencil id and depth 1..8;
-// measured with the library's kernels (2048x1024x80 chunks in 3D, 38400-wide
-// rows in 2D); depths not measured are interpolated between measured ones.
-constexpr double kRateF32[8][8] = {
-    {590, 1150, 1650, 2139, 2340, 2550, 2750, 2958},  // 2D star r1
-    {589, 1124, 1600, 2027, 2020, 2015, 2010, 2002},  // 2D box r1
-    {562, 819, 810, 795, 0, 0, 0, 0},                 // 2D box r2
-    {426, 408, 390, 368, 0, 0, 0, 0},                 // 2D box r3
-    {233, 222, 206, 191, 0, 0, 0, 0},                 // 2D box r4
-    {527, 1098, 1367, 1239, 0, 0, 0, 0},              // 3D star r1
-    {539, 801, 0, 0, 0, 0, 0, 0},                     // 3D star r2
-    {496, 694, 649, 528, 0, 0, 0, 0},                 // 3D box r1
-};
 
 struct Sim {
   double bw_in, bw_out, bw_d2d, launch_s;
@@ -54,13 +40,9 @@ void default_machine(const Plan &P, so2dr_machine *m) {
   m->launch_us = 8.0;
   m->kcopy_gbps = 77.0;      // copy kernels of 64 workgroups both ways, beside stencil kernels
   m->kcopy_out_gbps = 88.0;  // DMA in, copy kernels out
+  // measured per storage type, stencil and depth (rates.hpp)
   const int md = max_depth(P.dtype, P.stencil);
-  for (int k = 1; k <= 8; ++k) {
-    double g = (P.stencil >= 0 && P.stencil < 8) ? kRateF32[P.stencil][k - 1] : 0.0;
-    if (P.dtype == SO2DR_F64) g *= 0.5;  // twice the bytes, half the FMA rate
-    if (P.dtype == SO2DR_BF16 || P.dtype == SO2DR_F16) g *= k == 1 ? 1.5 : 1.1;  // half the bytes
-    m->gupd[k - 1] = k <= md ? g : 0.0;
-  }
+  for (int k = 1; k <= 8; ++k) m->gupd[k - 1] = k <= md ? kernel_rate(P.dtype, P.stencil, k) : 0.0;
 }
 
 namespace {

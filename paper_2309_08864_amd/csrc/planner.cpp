@@ -26,6 +26,7 @@
 #include "aux.hpp"
 #include "depths.hpp"
 #include "plan.hpp"
+#include "rates.hpp"
 
 namespace so2dr {
 
@@ -358,19 +359,13 @@ int make_plan(const so2dr_desc &D, Plan *P) {
     }
     P->k_on = std::min(D.k_on, P->K);
   } else {
-    // fused levels with the best measured update rate per launch on MI355X:
-    // 3D: 3 for the 7-point star, 2 for the 13-point star and the 27-point
-    // box; 2D: 8 for the 5-point star, 4 / 2 for the radius-1 / radius-2 box,
-    // 1 for wider boxes (their kernels are bound by arithmetic, and fusing
-    // only adds the tile-edge recomputation)
-    int pref = 2;
-    if (P->ndim == 3)
-      pref = P->r == 1 && P->shape == SO2DR_STAR ? 3 : 2;
-    else if (P->shape == SO2DR_STAR)
-      pref = 8;
-    else
-      pref = P->r == 1 ? 4 : (P->r == 2 ? 2 : 1);
-    P->k_on = std::max(1, std::min({pref, P->max_k_on, P->K}));
+    // the fused depth with the best measured update rate per launch on
+    // MI355X for this stencil and storage type (rates.hpp): e.g. FP32 3 for
+    // the 7-point star, 2 for the 13-point star and the 27-point box, 8 for
+    // the 2D 5-point star, 1 for the widest boxes (bound by arithmetic:
+    // fusing only adds tile-edge recomputation)
+    const int pref = preferred_depth(P->dtype, P->stencil, P->max_k_on);
+    P->k_on = std::max(1, std::min(pref, P->K));
   }
   P->budget = D.device_budget_bytes;
   P->adjoint = D.adjoint != 0;
