@@ -127,13 +127,14 @@ def test_c1_2d5pt_full():
     assert torch.equal(hi, h)
 
 
-def _check_bits(u0_np, got_np, offs, w, T, per, boxes, storage, tag):
+def _check_bits(u0_np, got_np, offs, w, T, per, boxes, storage, tag, round_after=None):
     """Sampled boxes bit for bit against the C model of the documented
     arithmetic (light-cone windows; the grid's interior boxes come from the
     kernels' interior path)."""
     from oracle import emulator
     for lo, hi in boxes:
-        ref = emulator.sweep_bits_box_from_field(u0_np, offs, w, T, lo, hi, storage, per)
+        ref = emulator.sweep_bits_box_from_field(u0_np, offs, w, T, lo, hi, storage, per,
+                                                 round_after=round_after)
         g = got_np[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
         g = np.ascontiguousarray(g.float().numpy() if isinstance(g, torch.Tensor) else g,
                                  dtype=np.float32)
@@ -225,9 +226,10 @@ def test_c3_3d27pt_full():
 
 
 def test_c4_3d13pt_full_precision():
-    """2048^3 13-point star in BF16, FP16 and FP32 storage (the FP32 field,
-    from the FP64 recipe rounded once, is the input; BF16 / FP16 inputs are
-    its roundings).  Per storage type: the workload's plan (K = 8, 32 chunks)
+    """2048^3 13-point star in BF16 (rounded every step and at store), FP16
+    and FP32 storage (the FP32 field, from the FP64 recipe rounded once, is
+    the input; BF16 / FP16 inputs are its roundings).  Per storage type and
+    rounding: the workload's plan (K = 8, 32 chunks)
     and, for FP32, also the cost model's plan (K = 24, 19 chunks, 1 slot)
     are bit-identical to the in-core run of that type; sampled boxes are
     bit-identical to the arithmetic model and, against the FP64 oracle run
@@ -252,7 +254,10 @@ def test_c4_3d13pt_full_precision():
     base = dict(ndim=3, nx=wl.nx, ny=wl.ny, nz=wl.nz, shape="star", radius=2, weights=list(w),
                 T=wl.T)
     dts = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32}
-    for name in ("bf16", "f16", "f32"):
+    own_refs = {}
+    for name, rounding in (("bf16", "every_step"), ("bf16", "at_store"), ("f16", "every_step"),
+                           ("f32", "every_step")):
+        tag = f"c4 {name}" + (" at store" if rounding == "at_store" else "")
         h = _pinned(shp, dts[name])
 
         def load():
@@ -260,13 +265,16 @@ def test_c4_3d13pt_full_precision():
                 h[z0:z0 + 64].copy_(tm[z0:z0 + 64])
 
         load()
-        refs_own = refs32 if name == "f32" else \
-            [oracle.sweep_box_from_field(h, offs, w, wl.T, lo, hi) for lo, hi in boxes]
+        if name not in own_refs:
+            own_refs[name] = refs32 if name == "f32" else \
+                [oracle.sweep_box_from_field(h, offs, w, wl.T, lo, hi) for lo, hi in boxes]
+        refs_own = own_refs[name]
         p = Plan(storage=name, tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, budget=wl.budget,
-                 **base).bind()
+                 rounding=rounding, **base).bind()
+        info = p.info()
         st = p.run(h)
         p.close()
-        _log(f"c4 {name} K=8 d=32: {st['wall_ms']:.0f} ms")
+        _log(f"{tag} K=8 d=32: {st['wall_ms']:.0f} ms")
         unit = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}[name]
         worst_arith, worst_total = 0.0, 0.0
         for k, ((lo, hi), r32, ref_own) in enumerate(zip(boxes, refs32, refs_own)):
@@ -277,14 +285,16 @@ def test_c4_3d13pt_full_precision():
             # the per-step roundings summed: T (u_storage + P 2^-24) max|u0|
             bound = wl.T * (unit + 13 * 2.0 ** -24) * max_u0
             worst_arith = max(worst_arith, err)
-            assert err <= bound, f"c4 {name}: box {lo} max err {err:.3e} > bound {bound:.3e}"
-        _log(f"c4 {name}: worst total rel L2 vs FP64 oracle (FP32 input) {worst_total:.3e}; "
+            assert err <= bound, f"{tag}: box {lo} max err {err:.3e} > bound {bound:.3e}"
+        _log(f"{tag}: worst total rel L2 vs FP64 oracle (FP32 input) {worst_total:.3e}; "
              f"worst arithmetic max err {worst_arith:.3e}")
         if name == "f32":
             assert worst_total <= 1e-5
         ooc = h.clone()                  # pageable copy of the out-of-core result
         load()
-        _check_bits(h, ooc, offs, w, wl.T, (0, 0, 0), boxes, name, f"c4 {name}")
+        from helpers import store_steps
+        ra = store_steps(wl.T, wl.tb_depth, info["k_on"]) if rounding == "at_store" else None
+        _check_bits(h, ooc, offs, w, wl.T, (0, 0, 0), boxes, name, tag, round_after=ra)
         if name == "f32":
             p = Plan(storage=name, tb_depth=24, n_chunks=19, k_on=2, n_slots=1, budget=wl.budget,
                      **base).bind()
@@ -296,13 +306,15 @@ def test_c4_3d13pt_full_precision():
             assert torch.equal(h, ooc), "c4 f32: the cost model's plan differs from K=8 d=32"
             load()
         esz = h.element_size()
-        pin = Plan(storage=name, tb_depth=wl.T, n_chunks=1,
+        # (at store: the same k_on, and K = 8 a multiple of it, give the same
+        # store schedule in and out of core)
+        pin = Plan(storage=name, tb_depth=wl.T, n_chunks=1, k_on=info["k_on"], rounding=rounding,
                    budget=2 * wl.nx * wl.ny * wl.nz * esz + (2 << 30), **base).bind()
         st = pin.run(h)
         pin.close()
-        _log(f"c4 {name} in-core: {st['wall_ms']:.0f} ms")
-        assert torch.equal(h, ooc), f"c4 {name}: out-of-core differs from in-core"
-        _log(f"c4 {name}: out-of-core == in-core bit for bit")
+        _log(f"{tag} in-core: {st['wall_ms']:.0f} ms")
+        assert torch.equal(h, ooc), f"{tag}: out-of-core differs from in-core"
+        _log(f"{tag}: out-of-core == in-core bit for bit")
         del h, ooc
         gc.collect()
         if hasattr(torch._C, "_host_emptyCache"):
@@ -362,3 +374,50 @@ def test_c5_adjoint_full():
     e_box = rel_l2(g, lam0)
     _log(f"c5 grad_u0 sampled box rel L2 vs FP64 oracle {e_box:.2e}")
     assert e_box <= 1e-4
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_paper_box2d_full(r):
+    """The paper's out-of-core workloads at full size (box2d{r}r, 38400^2
+    FP32, 640 steps, 4 chunks, S_TB 160/160/80/40, 10 GB budget): the SO2DR
+    plan and the ResReu comparison plan are bit-identical to the in-core
+    run; for radius 1 and 2 also sampled boxes against the FP64 oracle (the
+    light cone of 640 steps: windows of 1281^2 and 2561^2 cells)."""
+    wl = WL[f"paper_box2d{r}r"]
+    offs = stencil_offsets(2, "box", r)
+    w = workloads.fp32_rounded(_weights(wl, offs))
+    shp = (wl.ny, wl.nx)
+    h_in = _pinned(shp, torch.float32)
+    workloads.uniform_into(h_in.numpy(), wl.seed)
+    kw = dict(ndim=2, nx=wl.nx, ny=wl.ny, nz=1, shape="box", radius=r, weights=list(w), T=wl.T)
+    outs = {}
+    for name, over in (("in-core", dict(tb_depth=wl.T, n_chunks=1, budget=24 << 30)),
+                       ("so2dr", dict(tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, budget=wl.budget)),
+                       ("resreu", dict(tb_depth=wl.tb_depth, n_chunks=wl.n_chunks, budget=wl.budget,
+                                       method="resreu"))):
+        p = Plan(**kw, **over).bind()
+        info = p.info()
+        h = _pinned(shp, torch.float32) if name != "resreu" else outs.pop("so2dr_buf")
+        st = p.run_steps(h_in, h, wl.T)
+        p.close()
+        _log(f"box2d{r}r {name}: {st['wall_ms']:.0f} ms, k_on {info['k_on']}, {info['n_chunks']} chunks")
+        if name == "in-core":
+            outs["ref"] = h
+        else:
+            assert torch.equal(h, outs["ref"]), f"box2d{r}r: {name} differs from in-core"
+            _log(f"box2d{r}r {name} == in-core bit for bit")
+            if name == "so2dr":
+                if r <= 2:
+                    rng = np.random.default_rng(5 + r)
+                    # a corner each way and a box across the middle chunk boundary
+                    x0 = int(rng.integers(0, wl.nx - 2))
+                    corners = [(0, 0), (wl.nx - 2, wl.ny - 2), (x0, wl.ny // 2 - 1)]
+                    boxes = [((x, y, 0), (x + 2, y + 2, 1)) for x, y in corners]
+                    worst = 0.0
+                    for lo, hi in boxes:
+                        ref = oracle.sweep_box_from_field(h_in.numpy(), offs, w, wl.T, lo, hi)
+                        g = h.numpy()[lo[1]:hi[1], lo[0]:hi[0]].astype(np.float64)
+                        worst = max(worst, rel_l2(g, ref[0] if ref.ndim == 3 else ref))
+                    _log(f"box2d{r}r: {len(boxes)} boxes, worst rel L2 vs FP64 oracle {worst:.3e}")
+                    assert worst <= 1e-5
+                outs["so2dr_buf"] = h
