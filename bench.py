@@ -185,44 +185,29 @@ def plan_for(wl, w, storage, args, K, d, k_on=0, slots=0, rounding="every_step")
 
 # ---------------------------------------------------------------- host link
 def link_probe(nbytes=1 << 30, reps=4):
-    """Pinned host <-> HBM copies by hipMemcpyAsync (PyTorch copies on two of
-    the library's streams): host -> HBM alone, HBM -> host alone, and both
-    directions at once.  GB/s = bytes moved / wall time."""
+    """Pinned host <-> HBM copies as the executor issues them
+    (so2dr_link_probe: hipMemcpyAsync on the library's copy-in and copy-out
+    streams): host -> HBM alone, HBM -> host alone, both directions at once.
+    GB/s = bytes moved / wall time, best of `reps`."""
+    import ctypes
     import torch
+    from paper_2309_08864_amd import _lib, pinned_empty
     from paper_2309_08864_amd.plan import _plan_streams
     n = nbytes // 4
-    # PyTorch's own pinned allocator: PyTorch issues non-blocking copies
-    # asynchronously only for memory it knows to be pinned
-    h_in = torch.empty((n,), dtype=torch.float32, pin_memory=True)
-    h_out = torch.empty((n,), dtype=torch.float32, pin_memory=True)
-    h_in.fill_(1.0)
-    d_in = torch.empty(n, dtype=torch.float32, device="cuda")
-    d_out = torch.ones(n, dtype=torch.float32, device="cuda")
+    h_a = pinned_empty((n,), torch.float32).fill_(1.0)
+    h_b = pinned_empty((n,), torch.float32)
+    d_a = torch.empty(n, dtype=torch.float32, device="cuda")
+    d_b = torch.ones(n, dtype=torch.float32, device="cuda")
     s_in, s_out = _plan_streams("cuda", 2)
-
-    def timed(h2d, d2h):
-        for rep in range(reps + 1):          # the first pass is a warm-up
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            if h2d:
-                with torch.cuda.stream(s_in):
-                    d_in.copy_(h_in, non_blocking=True)
-            if d2h:
-                with torch.cuda.stream(s_out):
-                    h_out.copy_(d_out, non_blocking=True)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if rep == 1:
-                best = dt
-            elif rep > 1:
-                best = min(best, dt)
-        return (h2d + d2h) * nbytes / best / 1e9
-
-    res = {"h2d_GBps": round(timed(1, 0), 2), "d2h_GBps": round(timed(0, 1), 2),
-           "duplex_GBps": round(timed(1, 1), 2),
-           "method": f"hipMemcpyAsync of {nbytes >> 20} MiB pinned buffers on two streams, best of {reps}"}
-    del h_in, h_out, d_in, d_out
-    return res
+    g = (ctypes.c_double * 3)()
+    _lib.check(_lib.lib().so2dr_link_probe(
+        ctypes.c_void_p(h_a.data_ptr()), ctypes.c_void_p(h_b.data_ptr()),
+        ctypes.c_void_p(d_a.data_ptr()), ctypes.c_void_p(d_b.data_ptr()), nbytes,
+        ctypes.c_void_p(s_in.cuda_stream), ctypes.c_void_p(s_out.cuda_stream), reps, g))
+    del h_a, h_b, d_a, d_b
+    return {"h2d_GBps": round(g[0], 2), "d2h_GBps": round(g[1], 2), "duplex_GBps": round(g[2], 2),
+            "method": f"so2dr_link_probe: hipMemcpyAsync of {nbytes >> 20} MiB pinned buffers on the "
+                      f"copy-in and copy-out streams, best of {reps}"}
 
 
 # ---------------------------------------------------------------- CPU oracle

@@ -236,12 +236,19 @@ int so2dr_plan_get_deps(const struct so2dr_plan *plan, int n_streams, int32_t *s
 int so2dr_plan_bind(struct so2dr_plan *plan, void *dev_arena, size_t arena_bytes,
                     void *const *streams, int n_streams);
 
+/* Testing aid for the failure path: the plan's next so2dr_run /
+ * so2dr_run_steps stops with E_HIP after enqueuing n_ops operations of its
+ * schedule (so2dr_plan_get_ops order), as if the HIP runtime had refused the
+ * next one; -1 (the default) never.  One run only.  Errors: E_INVALID. */
+int so2dr_plan_set_fail_after(struct so2dr_plan *plan, int64_t n_ops);
+
 /* Enable (1) or disable (0) per-operation HIP event timing in so2dr_stats. */
 int so2dr_plan_set_timing(struct so2dr_plan *plan, int enable);
 
 /* Run the plan's T steps: host_u holds u_0 on entry and u_T on return, in
  * place (nx*ny*nz elements of the storage type, pinned).  Synchronous: the
- * array may be reused when the call returns.  st may be NULL.
+ * array may be reused when the call returns, also after a failure (the work
+ * already queued is drained first).  st may be NULL.
  * Errors: E_UNBOUND, E_NOT_PINNED, E_HIP (host contents then undefined;
  * st->rounds_done tells how many rounds completed). */
 int so2dr_run(struct so2dr_plan *plan, void *host_u, so2dr_stats *st);
@@ -353,6 +360,16 @@ int so2dr_plan_suggest(const so2dr_desc *desc, const so2dr_machine *m, so2dr_des
  * or beyond the cut axis, null pointers, reps < 1), E_UNSUPPORTED, E_HIP. */
 int so2dr_kernel_bench(const struct so2dr_plan *plan, int levels, void *dev_in, void *dev_out,
                        int64_t in_planes, int reps, void *stream, double *ms);
+
+/* Host-link rates with the copies the executor issues (measurement): bytes
+ * from pinned host_a to device dev_a on stream_in (host -> HBM), from dev_b
+ * to pinned host_b on stream_out (HBM -> host), each alone and both at once;
+ * gbps[0..2] receive the best of `reps` passes (after one warm-up pass) in
+ * GB/s (1e9 bytes; both at once: the two directions' bytes together).  The
+ * caller owns all four buffers (bytes each) and the two distinct streams.
+ * Errors: E_INVALID, E_NOT_PINNED, E_HIP. */
+int so2dr_link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes,
+                     void *stream_in, void *stream_out, int reps, double *gbps);
 
 /* Message describing the last error on this thread ("" if none). */
 const char *so2dr_last_error(void);

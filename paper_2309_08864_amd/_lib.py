@@ -24,7 +24,8 @@ EXPORTS = ["so2dr_plan_create", "so2dr_plan_destroy", "so2dr_plan_get_info",
            "so2dr_plan_set_timing", "so2dr_run", "so2dr_run_steps", "so2dr_adjoint_run",
            "so2dr_last_error", "so2dr_version", "so2dr_machine_default", "so2dr_plan_predict",
            "so2dr_plan_suggest", "so2dr_host_alloc", "so2dr_host_free", "so2dr_run_noalloc",
-           "so2dr_plan_get_deps", "so2dr_kernel_bench"]
+           "so2dr_plan_get_deps", "so2dr_kernel_bench", "so2dr_plan_set_fail_after",
+           "so2dr_link_probe"]
 
 MAX_WAITS = 4   # SO2DR_MAX_WAITS
 
@@ -111,6 +112,9 @@ def lib():
                                          ctypes.POINTER(ctypes.c_double)]
         L.so2dr_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp), i32]
         L.so2dr_plan_set_timing.argtypes = [vp, i32]
+        L.so2dr_plan_set_fail_after.argtypes = [vp, i64]
+        L.so2dr_link_probe.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp, vp, i32,
+                                       ctypes.POINTER(ctypes.c_double)]
         L.so2dr_run.argtypes = [vp, vp, ctypes.POINTER(Stats)]
         L.so2dr_run_noalloc.argtypes = [vp, vp, ctypes.POINTER(vp), i32, ctypes.POINTER(Stats)]
         L.so2dr_run_steps.argtypes = [vp, vp, vp, i32, ctypes.POINTER(Stats)]
@@ -131,7 +135,7 @@ def lib():
                   "so2dr_run_steps", "so2dr_adjoint_run", "so2dr_machine_default",
                   "so2dr_plan_predict", "so2dr_plan_suggest", "so2dr_host_alloc",
                   "so2dr_host_free", "so2dr_run_noalloc", "so2dr_plan_get_deps",
-                  "so2dr_kernel_bench"):
+                  "so2dr_kernel_bench", "so2dr_plan_set_fail_after", "so2dr_link_probe"):
             getattr(L, f).restype = i32
         _LIB = L
     return _LIB

@@ -24,6 +24,8 @@ double predict_seconds(const Plan &P, const so2dr_machine &m, int steps);
 int suggest(const so2dr_desc &in, const so2dr_machine *mp, so2dr_desc *out, double *pred_ms);
 int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t in_planes, int reps,
                  hipStream_t s, double *ms);
+int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, hipStream_t s_in,
+               hipStream_t s_out, int reps, double *gbps);
 }  // namespace so2dr
 
 using so2dr::set_error;
@@ -250,6 +252,17 @@ int so2dr_plan_set_timing(so2dr_plan *plan, int enable) {
   GUARD_END
 }
 
+int so2dr_plan_set_fail_after(so2dr_plan *plan, int64_t n_ops) {
+  GUARD_BEGIN
+  if (!plan || n_ops < -1) {
+    set_error("null plan or n_ops < -1");
+    return SO2DR_E_INVALID;
+  }
+  plan->p.fail_after_ops = n_ops;
+  return SO2DR_OK;
+  GUARD_END
+}
+
 int so2dr_run(so2dr_plan *plan, void *host_u, so2dr_stats *st) {
   GUARD_BEGIN
   if (!plan) {
@@ -342,6 +355,14 @@ int so2dr_kernel_bench(const so2dr_plan *plan, int levels, void *dev_in, void *d
   }
   return so2dr::kernel_bench(plan->p, levels, dev_in, dev_out, in_planes, reps,
                              static_cast<hipStream_t>(stream), ms);
+  GUARD_END
+}
+
+int so2dr_link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes,
+                     void *stream_in, void *stream_out, int reps, double *gbps) {
+  GUARD_BEGIN
+  return so2dr::link_probe(host_a, host_b, dev_a, dev_b, bytes, static_cast<hipStream_t>(stream_in),
+                           static_cast<hipStream_t>(stream_out), reps, gbps);
   GUARD_END
 }
 

@@ -43,6 +43,7 @@ struct Plan {
   std::vector<hipStream_t> streams;
   bool bound = false;
   bool timing = false;
+  int64_t fail_after_ops = -1;     // testing aid: the next run fails after this many ops
   std::vector<hipEvent_t> ev_rs, ev_d2h, ev_h2d, ev_comp;   // adjoint sweep: round * d + chunk
   std::vector<hipEvent_t> ev_op;           // forward runs: completion of op k (when awaited)
   std::vector<hipEvent_t> ev_t;            // timing pairs, 2 per op

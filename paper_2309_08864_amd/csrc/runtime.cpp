@@ -29,6 +29,7 @@
 #include <chrono>
 #include <cstring>
 #include <map>
+#include <string>
 
 #include "launch.hpp"
 #include "aux.hpp"
@@ -303,10 +304,16 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
   // every operation is enqueued here; on a failure part-way, the work
   // already queued is drained before returning (so the caller may release
   // the arena at once)
+  const int64_t fail_at = P.fail_after_ops;
+  P.fail_after_ops = -1;   // one run only
   auto enqueue = [&]() -> int {
   for (size_t k = 0; k < ops.size(); ++k) {
     const so2dr_op &op = ops[k];
     hipStream_t s = P.streams[strm[k]];
+    if ((int64_t)k == fail_at) {
+      set_error("injected failure after " + std::to_string(k) + " operations (so2dr_plan_set_fail_after)");
+      return SO2DR_E_HIP;
+    }
     // cross-stream waits, enqueued before the op's timing start
     for (int i = 0; i < kMaxWaits; ++i) {
       const int64_t x = waits[k * kMaxWaits + i];
@@ -398,7 +405,11 @@ int execute(Plan &P, const void *host_in, void *host_out, int steps, so2dr_stats
   };
   rc = enqueue();
   if (rc) {
+    // what was queued has finished: rounds_done counts the rounds whose
+    // copy-out of the last chunk was queued
     drain_streams(P);
+    S.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (st) *st = S;
     return rc;
   }
   for (hipStream_t s : P.streams) HIPCHK(hipStreamSynchronize(s));
@@ -495,6 +506,36 @@ int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t
     return SO2DR_E_HIP;
   }
   *ms = (double)t / reps;
+  return SO2DR_OK;
+}
+
+int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, hipStream_t s_in,
+               hipStream_t s_out, int reps, double *gbps) {
+  if (!host_a || !host_b || !dev_a || !dev_b || !gbps || bytes == 0 || reps < 1 || s_in == s_out) {
+    set_error("null buffer or output, zero bytes, reps < 1, or one stream for both directions");
+    return SO2DR_E_INVALID;
+  }
+  int rc = check_pinned(host_a, bytes, "host_a");
+  if (rc) return rc;
+  rc = check_pinned(host_b, bytes, "host_b");
+  if (rc) return rc;
+  // mode 0: host -> HBM alone; 1: HBM -> host alone; 2: both at once
+  for (int mode = 0; mode < 3; ++mode) {
+    double best = 0.0;
+    for (int rep = 0; rep <= reps; ++rep) {   // the first pass warms up
+      HIPCHK(hipStreamSynchronize(s_in));
+      HIPCHK(hipStreamSynchronize(s_out));
+      const auto t0 = std::chrono::steady_clock::now();
+      if (mode != 1) HIPCHK(hipMemcpyAsync(dev_a, host_a, bytes, hipMemcpyHostToDevice, s_in));
+      if (mode != 0) HIPCHK(hipMemcpyAsync(host_b, dev_b, bytes, hipMemcpyDeviceToHost, s_out));
+      HIPCHK(hipStreamSynchronize(s_in));
+      HIPCHK(hipStreamSynchronize(s_out));
+      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      const double rate = (mode == 2 ? 2.0 : 1.0) * (double)bytes / sec / 1e9;
+      if (rep > 0 && rate > best) best = rate;
+    }
+    gbps[mode] = best;
+  }
   return SO2DR_OK;
 }
 

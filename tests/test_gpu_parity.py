@@ -436,3 +436,46 @@ def test_f32_row_length_fallback_kernel(ndim, shape, r):
     for k_on in range(1, min(3, maxk) + 1):
         got, _, _ = gpu_run(dict(base, tb_depth=K, n_chunks=d, k_on=k_on), us)
         assert torch.equal(got, incore), (ndim, shape, r, k_on)
+
+
+def test_failure_mid_run_drains_and_reports_rounds():
+    """A run that stops part-way -- an E_HIP injected from the host before
+    the first operation of round 2 (so2dr_plan_set_fail_after) -- returns
+    after draining what it queued, reports the two rounds completed in its
+    stats, and leaves the plan usable: the next run equals the in-core
+    result bit for bit.  The same for a gradient whose forward pass stops."""
+    import ctypes
+    from paper_2309_08864_amd import Plan, _lib
+    rng = np.random.default_rng(61)
+    offs = _offsets(3, "star", 1)
+    w = fp32_weights(_weights(offs, rng))
+    nx, ny, nz, T = 96, 40, 48, 9
+    us = to_storage(rng.random((nz, ny, nx)), "f32")
+    base = dict(ndim=3, nx=nx, ny=ny, nz=nz, shape="star", radius=1, weights=list(w), T=T,
+                budget=1 << 30)
+    incore, _, _ = gpu_run(dict(base, tb_depth=T, n_chunks=1), us)
+    p = Plan(tb_depth=3, n_chunks=4, **base).bind()
+    ops = p.ops()
+    first_r2 = next(k for k, o in enumerate(ops) if o["round"] == 2)
+    L = _lib.lib()
+    assert L.so2dr_plan_set_fail_after(p._h, first_r2) == 0
+    h = pinned_copy(us)
+    st = _lib.Stats()
+    rc = L.so2dr_run(p._h, ctypes.c_void_p(h.data_ptr()), ctypes.byref(st))
+    assert rc == _lib.E_HIP and "injected" in L.so2dr_last_error().decode()
+    assert st.rounds_done == 2
+    h2 = pinned_copy(us)
+    p.run(h2)
+    assert torch.equal(h2, incore)
+    p.close()
+    # gradient: the forward pass inside so2dr_adjoint_run stops, then a clean call
+    y = to_storage(rng.random((nz, ny, nx)), "f32")
+    pa = Plan(tb_depth=3, n_chunks=4, adjoint=True, **base).bind()
+    assert L.so2dr_plan_set_fail_after(pa._h, 5) == 0
+    with pytest.raises(_lib.So2drError, match="E_HIP"):
+        pa.adjoint(pinned_copy(us), pinned_copy(y), 4)
+    loss, gu, gw, _ = pa.adjoint(pinned_copy(us), pinned_copy(y), 4)
+    pa.close()
+    rl, rgu, rgw, _ = oracle.adjoint(us.double().numpy(), y.double().numpy(), offs, w, T)
+    assert abs(loss - rl) <= 1e-4 * abs(rl)
+    assert rel_l2(gu.double().numpy(), rgu) <= 1e-4
