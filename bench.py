@@ -184,11 +184,12 @@ def plan_for(wl, w, storage, args, K, d, k_on=0, slots=0, rounding="every_step")
 
 
 # ---------------------------------------------------------------- host link
-def link_probe(nbytes=1 << 30, reps=4):
+def link_probe(nbytes=4 << 30, pieces=8, reps=3):
     """Pinned host <-> HBM copies as the executor issues them
     (so2dr_link_probe: hipMemcpyAsync on the library's copy-in and copy-out
-    streams): host -> HBM alone, HBM -> host alone, both directions at once.
-    GB/s = bytes moved / wall time, best of `reps`."""
+    streams, `pieces` copies per direction queued back to back, as a round
+    of chunks is): host -> HBM alone, HBM -> host alone, both directions at
+    once.  GB/s = bytes moved / wall time, best of `reps`."""
     import ctypes
     import torch
     from paper_2309_08864_amd import _lib, pinned_empty
@@ -202,12 +203,12 @@ def link_probe(nbytes=1 << 30, reps=4):
     g = (ctypes.c_double * 3)()
     _lib.check(_lib.lib().so2dr_link_probe(
         ctypes.c_void_p(h_a.data_ptr()), ctypes.c_void_p(h_b.data_ptr()),
-        ctypes.c_void_p(d_a.data_ptr()), ctypes.c_void_p(d_b.data_ptr()), nbytes,
+        ctypes.c_void_p(d_a.data_ptr()), ctypes.c_void_p(d_b.data_ptr()), nbytes, pieces,
         ctypes.c_void_p(s_in.cuda_stream), ctypes.c_void_p(s_out.cuda_stream), reps, g))
     del h_a, h_b, d_a, d_b
     return {"h2d_GBps": round(g[0], 2), "d2h_GBps": round(g[1], 2), "duplex_GBps": round(g[2], 2),
-            "method": f"so2dr_link_probe: hipMemcpyAsync of {nbytes >> 20} MiB pinned buffers on the "
-                      f"copy-in and copy-out streams, best of {reps}"}
+            "method": f"so2dr_link_probe: {pieces} hipMemcpyAsync copies of {(nbytes // pieces) >> 20} "
+                      f"MiB per direction on the copy-in and copy-out streams, best of {reps}"}
 
 
 # ---------------------------------------------------------------- CPU oracle

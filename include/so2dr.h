@@ -363,12 +363,15 @@ int so2dr_kernel_bench(const struct so2dr_plan *plan, int levels, void *dev_in, 
 
 /* Host-link rates with the copies the executor issues (measurement): bytes
  * from pinned host_a to device dev_a on stream_in (host -> HBM), from dev_b
- * to pinned host_b on stream_out (HBM -> host), each alone and both at once;
+ * to pinned host_b on stream_out (HBM -> host), each as `pieces`
+ * hipMemcpyAsync calls of bytes / pieces queued back to back (the two
+ * directions interleaved), each direction alone and both at once;
  * gbps[0..2] receive the best of `reps` passes (after one warm-up pass) in
  * GB/s (1e9 bytes; both at once: the two directions' bytes together).  The
  * caller owns all four buffers (bytes each) and the two distinct streams.
- * Errors: E_INVALID, E_NOT_PINNED, E_HIP. */
-int so2dr_link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes,
+ * Errors: E_INVALID (also bytes not a multiple of pieces), E_NOT_PINNED,
+ * E_HIP. */
+int so2dr_link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, int pieces,
                      void *stream_in, void *stream_out, int reps, double *gbps);
 
 /* Message describing the last error on this thread ("" if none). */

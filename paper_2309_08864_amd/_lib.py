@@ -113,7 +113,7 @@ def lib():
         L.so2dr_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(vp), i32]
         L.so2dr_plan_set_timing.argtypes = [vp, i32]
         L.so2dr_plan_set_fail_after.argtypes = [vp, i64]
-        L.so2dr_link_probe.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp, vp, i32,
+        L.so2dr_link_probe.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, i32, vp, vp, i32,
                                        ctypes.POINTER(ctypes.c_double)]
         L.so2dr_run.argtypes = [vp, vp, ctypes.POINTER(Stats)]
         L.so2dr_run_noalloc.argtypes = [vp, vp, ctypes.POINTER(vp), i32, ctypes.POINTER(Stats)]

@@ -24,8 +24,8 @@ double predict_seconds(const Plan &P, const so2dr_machine &m, int steps);
 int suggest(const so2dr_desc &in, const so2dr_machine *mp, so2dr_desc *out, double *pred_ms);
 int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t in_planes, int reps,
                  hipStream_t s, double *ms);
-int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, hipStream_t s_in,
-               hipStream_t s_out, int reps, double *gbps);
+int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, int pieces,
+               hipStream_t s_in, hipStream_t s_out, int reps, double *gbps);
 }  // namespace so2dr
 
 using so2dr::set_error;
@@ -358,10 +358,10 @@ int so2dr_kernel_bench(const so2dr_plan *plan, int levels, void *dev_in, void *d
   GUARD_END
 }
 
-int so2dr_link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes,
+int so2dr_link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, int pieces,
                      void *stream_in, void *stream_out, int reps, double *gbps) {
   GUARD_BEGIN
-  return so2dr::link_probe(host_a, host_b, dev_a, dev_b, bytes, static_cast<hipStream_t>(stream_in),
+  return so2dr::link_probe(host_a, host_b, dev_a, dev_b, bytes, pieces, static_cast<hipStream_t>(stream_in),
                            static_cast<hipStream_t>(stream_out), reps, gbps);
   GUARD_END
 }

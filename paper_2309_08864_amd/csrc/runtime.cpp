@@ -509,12 +509,15 @@ int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t
   return SO2DR_OK;
 }
 
-int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, hipStream_t s_in,
-               hipStream_t s_out, int reps, double *gbps) {
-  if (!host_a || !host_b || !dev_a || !dev_b || !gbps || bytes == 0 || reps < 1 || s_in == s_out) {
-    set_error("null buffer or output, zero bytes, reps < 1, or one stream for both directions");
+int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t bytes, int pieces,
+               hipStream_t s_in, hipStream_t s_out, int reps, double *gbps) {
+  if (!host_a || !host_b || !dev_a || !dev_b || !gbps || bytes == 0 || reps < 1 || s_in == s_out ||
+      pieces < 1 || bytes % (size_t)pieces) {
+    set_error("null buffer or output, zero bytes, reps < 1, one stream for both directions, or bytes "
+              "not a multiple of pieces");
     return SO2DR_E_INVALID;
   }
+  const size_t piece = bytes / (size_t)pieces;
   int rc = check_pinned(host_a, bytes, "host_a");
   if (rc) return rc;
   rc = check_pinned(host_b, bytes, "host_b");
@@ -526,8 +529,17 @@ int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t byte
       HIPCHK(hipStreamSynchronize(s_in));
       HIPCHK(hipStreamSynchronize(s_out));
       const auto t0 = std::chrono::steady_clock::now();
-      if (mode != 1) HIPCHK(hipMemcpyAsync(dev_a, host_a, bytes, hipMemcpyHostToDevice, s_in));
-      if (mode != 0) HIPCHK(hipMemcpyAsync(host_b, dev_b, bytes, hipMemcpyDeviceToHost, s_out));
+      // the pieces of both directions are queued interleaved, as the
+      // executor queues one chunk's copy-in and an earlier chunk's copy-out
+      for (int k = 0; k < pieces; ++k) {
+        const size_t off = (size_t)k * piece;
+        if (mode != 1)
+          HIPCHK(hipMemcpyAsync(static_cast<char *>(dev_a) + off, static_cast<char *>(host_a) + off, piece,
+                                hipMemcpyHostToDevice, s_in));
+        if (mode != 0)
+          HIPCHK(hipMemcpyAsync(static_cast<char *>(host_b) + off, static_cast<char *>(dev_b) + off, piece,
+                                hipMemcpyDeviceToHost, s_out));
+      }
       HIPCHK(hipStreamSynchronize(s_in));
       HIPCHK(hipStreamSynchronize(s_out));
       const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
