@@ -164,10 +164,10 @@ inline bool march_fits(const LaunchParams &p) {
 }
 
 template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1,
-          bool RAS = false>
+          bool RAS = false, int HA = VX>
 int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   using A = typename Store<T>::A;
-  using G = StarTile<R, KL, NW, M, VX>;
+  using G = StarTile<R, KL, NW, M, VX, HA>;
   using S = Stencil<3, BOX, R>;
   if (p.npts != S::npts()) {
     if (msg) *msg = "weight count does not match the stencil";
@@ -201,7 +201,7 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
   // 2048x1024x80 chunks, fewer leave the last wave of workgroups short and
   // more re-read 2 KL R planes per extra segment.
   static std::atomic<int> per_cu{-1};
-  const void *kfn = (const void *)march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE, RAS>;
+  const void *kfn = (const void *)march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE, RAS, HA>;
   const int64_t slots = resident_wgs(kfn, NW * 64, &per_cu);
   plan_segments(span, (int64_t)a.ntx * a.nty, &a.zseg, &a.nseg, slots > 0 ? slots * 3 / 2 : kTargetWgs);
   const int64_t nwg = (int64_t)a.ntx * a.nty * a.nseg;
@@ -210,7 +210,7 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
     return -1;
   }
   const int64_t grid = xcd_grid(nwg);
-  hipLaunchKernelGGL((march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE, RAS>), dim3((unsigned)grid), dim3(NW * 64), 0,
+  hipLaunchKernelGGL((march3d_kernel<T, BOX, R, KL, NW, M, VX, HB, PF, WPE, RAS, HA>), dim3((unsigned)grid), dim3(NW * 64), 0,
                      stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -308,11 +308,19 @@ int launch_any(const LaunchParams &p, hipStream_t s, std::string *msg) {
     constexpr bool square = a32 && !BOX && R == 1 && KL == 2;
     constexpr bool tall = a32 && !BOX && ((R == 1 && KL == 3) || (R == 2 && KL == 2));
     constexpr int HB = march_lds<A, KL, 8, R, 2, 2>() <= 65536 ? 2 : 1;
+    // Star tiles of 1 KiB FP32 rows (2 KiB FP64) take a 64-byte x halo: each
+    // output row is then whole 128-byte lines.  Measured on 2048x1024
+    // planes: single-step launches 3-8 % faster (FP32 7- and 13-point, FP64)
+    // and the two-step 7-point launch 0-3 % faster than with the 4-cell halo,
+    // whose output rows share lines with the neighbouring tiles.  The
+    // 512-byte-row shapes of deeper fusion and the 27-point box lose more to
+    // the wider halo's arithmetic than they gain; 16-bit rows gain nothing.
+    constexpr int HA4 = BOX ? 4 : sizeof(T) == 4 ? 16 : sizeof(T) == 8 ? 8 : 4;
     if constexpr (wide) {
-      if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 16, 2, 4, 2, 2, 1, RAS>(p, s, msg);
+      if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 16, 2, 4, 2, 2, 1, RAS, HA4>(p, s, msg);
     } else {
       if constexpr (square)
-        if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 4, 2, 2, 1, RAS>(p, s, msg);
+        if (march_fits<T, 4>(p)) return launch_march_one<T, BOX, R, KL, 8, 4, 4, 2, 2, 1, RAS, HA4>(p, s, msg);
       if constexpr (tall)
         if (march_fits<T, 2>(p)) return launch_march_one<T, BOX, R, KL, 8, 6, 2, 2, 2, 1, RAS>(p, s, msg);
       if constexpr (march_lds<A, KL, 8, R, 2, HB>() <= kLdsMax && 2 * ((KL * R + 1) / 2) < 32 &&

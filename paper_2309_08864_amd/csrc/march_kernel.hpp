@@ -47,7 +47,7 @@ __device__ __forceinline__ void unroll_seq(F &&f, std::integer_sequence<int, I..
 
 constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool RAS, bool GH>
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool RAS, bool GH, int HA>
 __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> &a,
                                              typename Store<T>::A (*halo)[HB][NW][2 * R][64 * VX],
                                              int lane, int wave, int tx_i, int ty_i, int zo0, int zo1);
@@ -55,10 +55,12 @@ __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> 
 // WPE: waves per SIMD the register allocation must allow (caps VGPRs at
 // 512 / WPE).  RAS (round at store): levels below the last keep FP32 sums;
 // only the value a launch stores is rounded to the storage type.
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1, bool RAS = false>
+// HA: x-halo alignment in cells (StarTile).
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, int WPE = 1, bool RAS = false,
+          int HA = VX>
 __global__ __launch_bounds__(NW * 64, WPE) void march3d_kernel(const TbArgs<typename Store<T>::A> a) {
   using A = typename Store<T>::A;
-  using G = StarTile<R, KL, NW, M, VX>;
+  using G = StarTile<R, KL, NW, M, VX, HA>;
   __shared__ A halo[KL][HB][NW][2 * R][64 * VX];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -82,18 +84,18 @@ __global__ __launch_bounds__(NW * 64, WPE) void march3d_kernel(const TbArgs<type
                       (!a.per_y && (y_lo < 0 || y_lo + G::TY > a.ny)) || P0 - 2 * R < 0 ||
                       P0 + n_load + R > (int)a.n_axis;
   if (ghosts)
-    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, RAS, true>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
+    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, RAS, true, HA>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
   else
-    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, RAS, false>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
+    march3d_tile<T, BOX, R, KL, NW, M, VX, HB, PF, RAS, false, HA>(a, halo, lane, wave, tx_i, ty_i, zo0, zo1);
 }
 
-template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool RAS, bool GH>
+template <typename T, bool BOX, int R, int KL, int NW, int M, int VX, int HB, int PF, bool RAS, bool GH, int HA>
 __device__ __forceinline__ void march3d_tile(const TbArgs<typename Store<T>::A> &a,
                                              typename Store<T>::A (*halo)[HB][NW][2 * R][64 * VX],
                                              int lane, int wave, int tx_i, int ty_i, int zo0, int zo1) {
   using A = typename Store<T>::A;
   using S = Stencil<3, BOX, R>;
-  using G = StarTile<R, KL, NW, M, VX>;
+  using G = StarTile<R, KL, NW, M, VX, HA>;
   constexpr int W = 2 * R + 1;
   constexpr int RS = W * (PF / W + 1);  // prefetch ring: a multiple of W above PF
   static_assert(PF >= 1 && PF < RS, "prefetch distance must leave the consumed slot alone");

@@ -20,9 +20,9 @@ constexpr double kRate[4][8][8] = {
         {555, 787, 791, 807, 0, 0, 0, 0},                 // 2D box r2
         {424, 401, 394, 393, 0, 0, 0, 0},                 // 2D box r3
         {236, 225, 217, 200, 0, 0, 0, 0},                 // 2D box r4
-        {526, 1071, 1518, 1290, 0, 0, 0, 0},              // 3D star r1
-        {518, 902, 0, 0, 0, 0, 0, 0},                     // 3D star r2
-        {507, 793, 686, 529, 0, 0, 0, 0},                 // 3D box r1
+        {538, 1149, 1535, 1308, 0, 0, 0, 0},              // 3D star r1
+        {557, 884, 0, 0, 0, 0, 0, 0},                     // 3D star r2
+        {512, 792, 675, 530, 0, 0, 0, 0},                 // 3D box r1
     },
     {
         // F64
@@ -31,9 +31,9 @@ constexpr double kRate[4][8][8] = {
         {258, 494, 0, 0, 0, 0, 0, 0},
         {230, 239, 0, 0, 0, 0, 0, 0},
         {124, 117, 0, 0, 0, 0, 0, 0},
-        {251, 529, 0, 0, 0, 0, 0, 0},
-        {267, 248, 0, 0, 0, 0, 0, 0},
-        {252, 512, 0, 0, 0, 0, 0, 0},
+        {260, 533, 0, 0, 0, 0, 0, 0},
+        {270, 248, 0, 0, 0, 0, 0, 0},
+        {254, 511, 0, 0, 0, 0, 0, 0},
     },
     {
         // BF16
@@ -42,9 +42,9 @@ constexpr double kRate[4][8][8] = {
         {773, 832, 802, 799, 0, 0, 0, 0},
         {447, 413, 403, 384, 0, 0, 0, 0},
         {234, 224, 217, 198, 0, 0, 0, 0},
-        {995, 1357, 1495, 1244, 0, 0, 0, 0},
-        {767, 905, 0, 0, 0, 0, 0, 0},
-        {564, 834, 732, 516, 0, 0, 0, 0},
+        {1004, 1330, 1486, 1234, 0, 0, 0, 0},
+        {776, 914, 0, 0, 0, 0, 0, 0},
+        {555, 802, 717, 514, 0, 0, 0, 0},
     },
     {
         // F16
@@ -53,9 +53,9 @@ constexpr double kRate[4][8][8] = {
         {729, 788, 772, 783, 0, 0, 0, 0},
         {427, 395, 386, 373, 0, 0, 0, 0},
         {228, 219, 214, 195, 0, 0, 0, 0},
-        {984, 1269, 1419, 1161, 0, 0, 0, 0},
-        {730, 883, 0, 0, 0, 0, 0, 0},
-        {585, 777, 710, 511, 0, 0, 0, 0},
+        {993, 1290, 1414, 1162, 0, 0, 0, 0},
+        {710, 876, 0, 0, 0, 0, 0, 0},
+        {586, 769, 698, 510, 0, 0, 0, 0},
     },
 };
 

@@ -115,11 +115,15 @@ template <> struct VecIO<__half, 1> {
   static __device__ __forceinline__ void store(__half *p, const float *v) { Store<__half>::store(p, v[0]); }
 };
 
-template <int R, int KL, int NW, int M, int VX_>
+// HA: the x halo is rounded up to a multiple of HA cells (whole lanes at
+// least); with 64-cell-multiple rows and a 64-byte halo the output rows of
+// every tile start and end on 128-byte lines.
+template <int R, int KL, int NW, int M, int VX_, int HA = VX_>
 struct StarTile {
   static constexpr int VX = VX_;                        // x cells per lane
   static constexpr int TX = 64 * VX, TY = NW * M;
-  static constexpr int HX = (KL * R + VX - 1) / VX * VX;  // x halo, whole lanes
+  static constexpr int HX = (KL * R + HA - 1) / HA * HA;  // x halo
+  static_assert(HA % VX == 0, "the x halo must be whole lanes");
   static constexpr int HY = KL * R;
   static constexpr int OX = TX - 2 * HX, OY = TY - 2 * HY;
   static_assert(M >= R && R <= 2 * VX && OX > 0 && OY > 0, "tile too small for this depth");
