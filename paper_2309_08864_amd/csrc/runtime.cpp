@@ -500,6 +500,7 @@ int kernel_bench(const Plan &P, int levels, void *dev_in, void *dev_out, int64_t
   if (e == hipSuccess && rc == SO2DR_OK) e = hipEventElapsedTime(&t, e0, e1);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (rc || e != hipSuccess) (void)hipStreamSynchronize(s);  // the caller may free the buffers next
   if (rc) return rc;
   if (e != hipSuccess) {
     set_error(std::string("kernel timing: ") + hipGetErrorString(e));
@@ -522,33 +523,43 @@ int link_probe(void *host_a, void *host_b, void *dev_a, void *dev_b, size_t byte
   if (rc) return rc;
   rc = check_pinned(host_b, bytes, "host_b");
   if (rc) return rc;
-  // mode 0: host -> HBM alone; 1: HBM -> host alone; 2: both at once
-  for (int mode = 0; mode < 3; ++mode) {
-    double best = 0.0;
-    for (int rep = 0; rep <= reps; ++rep) {   // the first pass warms up
-      HIPCHK(hipStreamSynchronize(s_in));
-      HIPCHK(hipStreamSynchronize(s_out));
-      const auto t0 = std::chrono::steady_clock::now();
-      // the pieces of both directions are queued interleaved, as the
-      // executor queues one chunk's copy-in and an earlier chunk's copy-out
-      for (int k = 0; k < pieces; ++k) {
-        const size_t off = (size_t)k * piece;
-        if (mode != 1)
-          HIPCHK(hipMemcpyAsync(static_cast<char *>(dev_a) + off, static_cast<char *>(host_a) + off, piece,
-                                hipMemcpyHostToDevice, s_in));
-        if (mode != 0)
-          HIPCHK(hipMemcpyAsync(static_cast<char *>(host_b) + off, static_cast<char *>(dev_b) + off, piece,
-                                hipMemcpyDeviceToHost, s_out));
+  // mode 0: host -> HBM alone; 1: HBM -> host alone; 2: both at once.  On
+  // an error the copies already queued are drained before returning: the
+  // caller may free the buffers as soon as the call fails.
+  auto passes = [&]() -> int {
+    for (int mode = 0; mode < 3; ++mode) {
+      double best = 0.0;
+      for (int rep = 0; rep <= reps; ++rep) {   // the first pass warms up
+        HIPCHK(hipStreamSynchronize(s_in));
+        HIPCHK(hipStreamSynchronize(s_out));
+        const auto t0 = std::chrono::steady_clock::now();
+        // the pieces of both directions are queued interleaved, as the
+        // executor queues one chunk's copy-in and an earlier chunk's copy-out
+        for (int k = 0; k < pieces; ++k) {
+          const size_t off = (size_t)k * piece;
+          if (mode != 1)
+            HIPCHK(hipMemcpyAsync(static_cast<char *>(dev_a) + off, static_cast<char *>(host_a) + off, piece,
+                                  hipMemcpyHostToDevice, s_in));
+          if (mode != 0)
+            HIPCHK(hipMemcpyAsync(static_cast<char *>(host_b) + off, static_cast<char *>(dev_b) + off, piece,
+                                  hipMemcpyDeviceToHost, s_out));
+        }
+        HIPCHK(hipStreamSynchronize(s_in));
+        HIPCHK(hipStreamSynchronize(s_out));
+        const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const double rate = (mode == 2 ? 2.0 : 1.0) * (double)bytes / sec / 1e9;
+        if (rep > 0 && rate > best) best = rate;
       }
-      HIPCHK(hipStreamSynchronize(s_in));
-      HIPCHK(hipStreamSynchronize(s_out));
-      const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      const double rate = (mode == 2 ? 2.0 : 1.0) * (double)bytes / sec / 1e9;
-      if (rep > 0 && rate > best) best = rate;
+      gbps[mode] = best;
     }
-    gbps[mode] = best;
+    return SO2DR_OK;
+  };
+  rc = passes();
+  if (rc != SO2DR_OK) {
+    (void)hipStreamSynchronize(s_in);
+    (void)hipStreamSynchronize(s_out);
   }
-  return SO2DR_OK;
+  return rc;
 }
 
 int launch_tb(int dtype, const LaunchParams &p, hipStream_t stream, std::string *msg) {
