@@ -5,8 +5,8 @@ The march kernels run a second copy of their loop, without ghost handling,
 in every workgroup whose tile and plane segment touch no Dirichlet boundary;
 at the workloads' sizes that copy computes almost every cell.  These grids
 have at least three fully interior tiles along each in-plane axis for every
-tile shape (3D: 1032 x 160 with 248- or 120-column and 30- to 42-row output
-tiles; 2D: 4100-cell rows with 248- or 240-cell tiles) and chunks long enough
+tile shape (3D: 1032 x 160 with 224-, 240-, 248- or 120-column and 26- to
+42-row output tiles; 2D: 4100-cell rows with 248- or 240-cell tiles) and chunks long enough
 to be cut into several plane segments, so the interior copy, the boundary
 copy and their seams are all exercised.  The launcher's choice per fused
 depth (launch_any): 3D single steps (16 waves, 2 rows, 4 cells per lane);
@@ -15,12 +15,16 @@ two of the 13-point star (8, 6, 2); the other depths and the 27-point box
 (8, 4, 2); 2D rows with unrolled sums, and with shifted sums for the widest
 boxes (radius 4, and radius 3 at two levels).  Each case runs out of core
 (two chunks, two rounds of k_on steps) and is compared with the C model of
-the documented arithmetic (oracle/emulator_bits.c) bit for bit."""
+the documented arithmetic (oracle/emulator_bits.c) bit for bit; FP64 storage,
+which that model does not cover, against the FP64 oracle and bit for bit
+against its own in-core run."""
 import numpy as np
 import pytest
 
 import oracle
-from helpers import fp32_weights, gpu_run, np_shape, to_storage
+import torch
+
+from helpers import fp32_weights, gpu_run, np_shape, rel_l2, to_storage
 
 pytestmark = pytest.mark.gpu
 
@@ -79,3 +83,28 @@ def test_interior_tiles_periodic_xy_bit_exact(shape, r, k_on, storage):
     hold no ghosts, so every workgroup away from the cut axis's ends runs
     the interior copy."""
     _run_case(3, shape, r, k_on, storage, bc=(1, 1, 0))
+
+
+@pytest.mark.parametrize("shape,r,k_on", [("star", 1, 1), ("star", 1, 2), ("star", 2, 1), ("star", 2, 2),
+                                          ("box", 1, 1), ("box", 1, 2)])
+def test_interior_tiles_3d_f64(shape, r, k_on):
+    """FP64 storage and sums (single steps in the 2 KiB-row tiles with a
+    64-byte x halo, two steps in the 4-row tiles): out of core equals in
+    core bit for bit, and both are within FP64 rounding of the oracle."""
+    nx, ny, nz = 1032, 160, 120
+    rng = np.random.default_rng(2000 + 10 * r + k_on)
+    offs = oracle.stencil_offsets(3, shape, r)
+    w = rng.uniform(-1.0, 1.0, len(offs))
+    w = w / np.abs(w).sum()
+    u0 = rng.standard_normal((nz, ny, nx))
+    us = to_storage(u0, "f64")
+    T = 2 * k_on
+    kw = dict(ndim=3, nx=nx, ny=ny, nz=nz, shape=shape, radius=r, weights=list(w), T=T,
+              tb_depth=k_on, n_chunks=2, k_on=k_on, budget=1 << 30, storage="f64")
+    print(f"[f64 3D {shape} r={r} k_on={k_on}] {nx}x{ny}x{nz}", flush=True)
+    got, st, info = gpu_run(kw, us)
+    assert info["k_on"] == k_on and info["n_chunks"] == 2 and st["kernel_launches"] == 4
+    incore, _, _ = gpu_run(dict(kw, tb_depth=T, n_chunks=1, k_on=k_on), us)
+    assert torch.equal(got, incore)
+    ref = oracle.sweep(u0, offs, w, T)
+    assert rel_l2(got.numpy(), ref) <= 1e-13
