@@ -230,8 +230,9 @@ def test_c4_3d13pt_full_precision():
     and FP32 storage (the FP32 field, from the FP64 recipe rounded once, is
     the input; BF16 / FP16 inputs are its roundings).  Per storage type and
     rounding: the workload's plan (K = 8, 32 chunks)
-    and, for FP32, also the cost model's plan (K = 24, 19 chunks, 1 slot)
-    are bit-identical to the in-core run of that type; sampled boxes are
+    and, for FP32 and BF16, also the cost model's plan (FP32: K = 24, 19
+    chunks, 1 slot; BF16: K = 16, 22 chunks, k_on = 1) are bit-identical to
+    the in-core run of that type; sampled boxes are
     bit-identical to the arithmetic model and, against the FP64 oracle run
     from the same input, within the rigorous per-step rounding bound; the
     error against the oracle run from the FP32 input is reported.  At most
@@ -304,6 +305,18 @@ def test_c4_3d13pt_full_precision():
             p.close()
             _log(f"c4 f32 K=24 d=19 1 slot: {st['wall_ms']:.0f} ms")
             assert torch.equal(h, ooc), "c4 f32: the cost model's plan differs from K=8 d=32"
+            load()
+        if name == "bf16" and rounding == "every_step":
+            # the cost model's BF16 plan (round depth 16, 22 ragged chunks,
+            # single-step launches): every-step rounding makes the result
+            # independent of K, k_on and the chunking
+            p = Plan(storage=name, tb_depth=16, n_chunks=22, k_on=1, budget=wl.budget, **base).bind()
+            info2 = p.info()
+            assert (info2["tb_depth"], info2["n_chunks"], info2["k_on"]) == (16, 22, 1)
+            st = p.run(h)
+            p.close()
+            _log(f"c4 bf16 K=16 d=22 k_on=1 {info2['n_slots']} slots: {st['wall_ms']:.0f} ms")
+            assert torch.equal(h, ooc), "c4 bf16: the cost model's plan differs from K=8 d=32"
             load()
         esz = h.element_size()
         # (at store: the same k_on, and K = 8 a multiple of it, give the same
