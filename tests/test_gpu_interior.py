@@ -15,7 +15,8 @@ two of the 13-point star (8, 6, 2); the other depths and the 27-point box
 (8, 4, 2); 2D rows with unrolled sums, and with shifted sums for the widest
 boxes (radius 4, and radius 3 at two levels).  Each case runs out of core
 (two chunks, two rounds of k_on steps) and is compared with the C model of
-the documented arithmetic (oracle/emulator_bits.c) bit for bit; FP64 storage,
+the documented arithmetic (oracle/emulator_bits.c) bit for bit, for 16-bit
+storage also with rounding only where a launch stores; FP64 storage,
 which that model does not cover, against the FP64 oracle and bit for bit
 against its own in-core run."""
 import numpy as np
@@ -34,7 +35,7 @@ CASES_2D = [("star", 1, 4), ("star", 1, 8), ("box", 1, 4), ("box", 2, 2), ("box"
             ("box", 3, 2), ("box", 4, 1)]
 
 
-def _run_case(ndim, shape, r, k_on, storage, bc=(0, 0, 0)):
+def _run_case(ndim, shape, r, k_on, storage, bc=(0, 0, 0), rounding="every_step"):
     from oracle import emulator
     from paper_2309_08864_amd import Plan, So2drError
     nx, ny, nz = (1032, 160, 120) if ndim == 3 else (4100, 200, 1)
@@ -46,18 +47,23 @@ def _run_case(ndim, shape, r, k_on, storage, bc=(0, 0, 0)):
     us = to_storage(u0, storage)
     T = 2 * k_on
     kw = dict(ndim=ndim, nx=nx, ny=ny, nz=nz, shape=shape, radius=r, weights=list(w), T=T,
-              tb_depth=k_on, n_chunks=2, k_on=k_on, budget=1 << 30, storage=storage, bc=bc)
+              tb_depth=k_on, n_chunks=2, k_on=k_on, budget=1 << 30, storage=storage, bc=bc,
+              rounding=rounding)
     try:
         Plan(**kw).close()
     except So2drError as e:
         if "E_UNSUPPORTED" in str(e):
             pytest.skip(f"{storage} not built for the {ndim}D {shape} r={r} stencil at depth {k_on}")
         raise
-    print(f"[{storage} {ndim}D {shape} r={r} k_on={k_on} bc={bc}] {nx}x{ny}x{nz}", flush=True)
+    print(f"[{storage} {rounding} {ndim}D {shape} r={r} k_on={k_on} bc={bc}] {nx}x{ny}x{nz}", flush=True)
     got, st, info = gpu_run(kw, us)
     assert info["k_on"] == k_on and info["n_chunks"] == 2
     assert st["kernel_launches"] == 4
-    model = emulator.sweep_bits_c(us.float().numpy(), offs, w, T, storage, bc)
+    ra = None
+    if rounding == "at_store":
+        from helpers import store_steps
+        ra = store_steps(T, k_on, k_on)
+    model = emulator.sweep_bits_c(us.float().numpy(), offs, w, T, storage, bc, round_after=ra)
     g = np.ascontiguousarray(got.float().numpy())
     diff = int(np.sum(g.view(np.uint32) != model.view(np.uint32)))
     print(f"    cells differing from the model: {diff} of {g.size}", flush=True)
@@ -108,3 +114,13 @@ def test_interior_tiles_3d_f64(shape, r, k_on):
     assert torch.equal(got, incore)
     ref = oracle.sweep(u0, offs, w, T)
     assert rel_l2(got.numpy(), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("ndim,shape,r,k_on", [(3, "star", 1, 2), (3, "star", 1, 3), (3, "star", 2, 2),
+                                               (3, "box", 1, 2), (2, "star", 1, 4), (2, "box", 2, 2)])
+def test_interior_tiles_round_at_store(ndim, shape, r, k_on, storage):
+    """16-bit storage rounded only where a launch stores (the levels inside a
+    launch keep FP32 sums): bit for bit against the C model run with the
+    same store schedule, on the interior-tile grids."""
+    _run_case(ndim, shape, r, k_on, storage, rounding="at_store")
