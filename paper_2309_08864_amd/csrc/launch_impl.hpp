@@ -49,15 +49,11 @@ inline int64_t resident_wgs(const void *kernel, int threads, std::atomic<int> *p
   return (int64_t)per_cu * cus;
 }
 
-template <typename T, int NDIM, bool BOX, int R, int KL, bool RAS = false>
-int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
-  using A = typename Store<T>::A;
-  using G = Tile<NDIM, R, KL>;
-  using S = Stencil<NDIM, BOX, R>;
-  if (p.npts != S::npts()) {
-    if (msg) *msg = "weight count does not match the stencil";
-    return -1;
-  }
+// The argument block every kernel takes: buffers, geometry, planes and the
+// weights converted to the accumulation type.  Tile counts and segmenting
+// are the caller's.
+template <typename A>
+inline TbArgs<A> launch_args(const LaunchParams &p, int npts) {
   TbArgs<A> a{};
   a.in = p.in;
   a.out = p.out;
@@ -73,7 +69,20 @@ int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
   a.in_hi = p.in_hi;
   a.out_lo = p.out_lo;
   a.out_hi = p.out_hi;
-  for (int i = 0; i < S::npts(); ++i) a.w.w[i] = (A)p.weights[i];
+  for (int i = 0; i < npts; ++i) a.w.w[i] = (A)p.weights[i];
+  return a;
+}
+
+template <typename T, int NDIM, bool BOX, int R, int KL, bool RAS = false>
+int launch_one(const LaunchParams &p, hipStream_t stream, std::string *msg) {
+  using A = typename Store<T>::A;
+  using G = Tile<NDIM, R, KL>;
+  using S = Stencil<NDIM, BOX, R>;
+  if (p.npts != S::npts()) {
+    if (msg) *msg = "weight count does not match the stencil";
+    return -1;
+  }
+  TbArgs<A> a = launch_args<A>(p, S::npts());
   a.ntx = (int)((p.nx + G::OX - 1) / G::OX);
   a.nty = NDIM == 2 ? 1 : (int)((p.ny + G::OY - 1) / G::OY);
   const int64_t span = p.out_hi - p.out_lo;
@@ -115,22 +124,7 @@ int launch_col_one(const LaunchParams &p, hipStream_t stream, std::string *msg) 
     if (msg) *msg = "weight count does not match the stencil";
     return -1;
   }
-  TbArgs<A> a{};
-  a.in = p.in;
-  a.out = p.out;
-  a.buf_z0 = p.buf_z0;
-  a.out_z0 = p.out_z0;
-  a.plane = p.plane;
-  a.nx = p.nx;
-  a.ny = p.ny;
-  a.per_x = p.per_x;
-  a.per_y = p.per_y;
-  a.n_axis = p.n_axis;
-  a.in_lo = p.in_lo;
-  a.in_hi = p.in_hi;
-  a.out_lo = p.out_lo;
-  a.out_hi = p.out_hi;
-  for (int i = 0; i < S::npts(); ++i) a.w.w[i] = (A)p.weights[i];
+  TbArgs<A> a = launch_args<A>(p, S::npts());
   a.ntx = (int)((p.nx + G::OX - 1) / G::OX);
   a.nty = (int)((p.ny + G::OY - 1) / G::OY);
   const int64_t span = p.out_hi - p.out_lo;
@@ -177,22 +171,7 @@ int launch_march_one(const LaunchParams &p, hipStream_t stream, std::string *msg
     if (msg) *msg = "launch does not fit the march kernel's layout";
     return -1;
   }
-  TbArgs<A> a{};
-  a.in = p.in;
-  a.out = p.out;
-  a.buf_z0 = p.buf_z0;
-  a.out_z0 = p.out_z0;
-  a.plane = p.plane;
-  a.nx = p.nx;
-  a.ny = p.ny;
-  a.per_x = p.per_x;
-  a.per_y = p.per_y;
-  a.n_axis = p.n_axis;
-  a.in_lo = p.in_lo;
-  a.in_hi = p.in_hi;
-  a.out_lo = p.out_lo;
-  a.out_hi = p.out_hi;
-  for (int i = 0; i < S::npts(); ++i) a.w.w[i] = (A)p.weights[i];
+  TbArgs<A> a = launch_args<A>(p, S::npts());
   a.ntx = (int)((p.nx + G::OX - 1) / G::OX);
   a.nty = (int)((p.ny + G::OY - 1) / G::OY);
   const int64_t span = p.out_hi - p.out_lo;
@@ -233,22 +212,7 @@ int launch_march2d_one(const LaunchParams &p, hipStream_t stream, std::string *m
     if (msg) *msg = "launch does not fit the march kernel's layout";
     return -1;
   }
-  TbArgs<A> a{};
-  a.in = p.in;
-  a.out = p.out;
-  a.buf_z0 = p.buf_z0;
-  a.out_z0 = p.out_z0;
-  a.plane = p.plane;
-  a.nx = p.nx;
-  a.ny = p.ny;
-  a.per_x = p.per_x;
-  a.per_y = p.per_y;
-  a.n_axis = p.n_axis;
-  a.in_lo = p.in_lo;
-  a.in_hi = p.in_hi;
-  a.out_lo = p.out_lo;
-  a.out_hi = p.out_hi;
-  for (int i = 0; i < S::npts(); ++i) a.w.w[i] = (A)p.weights[i];
+  TbArgs<A> a = launch_args<A>(p, S::npts());
   a.ntx = (int)((p.nx + G::OX - 1) / G::OX);
   a.nty = 1;
   const int64_t span = p.out_hi - p.out_lo;
