@@ -320,9 +320,10 @@ def precision_leg(args, name="c4_3d13pt"):
     """The 13-point radius-2 workload (2048^3, T = 64, K = 8, 32 chunks, 8
     GiB) in FP32, BF16, FP16 and BF16 rounded at store.  The FP32 field (the
     FP64 recipe rounded once) is the input; BF16 / FP16 inputs are its
-    roundings.  Per storage type: one timed run after a small warm-up plan of
-    the same stencil and storage and one warm-up round of the plan itself;
-    GCell-updates/s; e_total = error against the
+    roundings.  Per storage type: two timed runs after a small warm-up plan
+    of the same stencil and storage and one warm-up round of the plan
+    itself; GCell-updates/s of the faster run (both listed); e_total = error
+    against the
     FP64 oracle run from the FP32 input, e_arith = against the oracle run
     from the storage-rounded input (sampled light-cone boxes: worst box and
     pooled over the boxes)."""
@@ -365,15 +366,21 @@ def precision_leg(args, name="c4_3d13pt"):
         # first copies of fresh page-locked memory are slow), then the input
         # again
         p.run_steps(h, h, wl.tb_depth)
-        fill_rounded(h, tm)
-        t1 = time.perf_counter()
-        st = p.run(h)
-        el = time.perf_counter() - t1
+        runs = []
+        for rep in range(2):
+            fill_rounded(h, tm)
+            t1 = time.perf_counter()
+            st = p.run(h)
+            runs.append((time.perf_counter() - t1, st))
+            if rep == 0:       # the result is the same bits every run
+                e_tot_w, e_tot = _errors(h, refs32, boxes)
+                e_ar_w, e_ar = _errors(h, refs_own[storage], boxes)
         p.close()
-        e_tot_w, e_tot = _errors(h, refs32, boxes)
-        e_ar_w, e_ar = _errors(h, refs_own[storage], boxes)
+        el, st = min(runs, key=lambda r: r[0])
         key = storage + ("_round_at_store" if rounding == "at_store" else "")
-        out[key] = {"GCells": round(wl.cells * wl.T / el / 1e9, 2), "wall_ms": round(st["wall_ms"], 1),
+        out[key] = {"GCells": round(wl.cells * wl.T / el / 1e9, 2),
+                    "runs_GCells": [round(wl.cells * wl.T / e / 1e9, 2) for e, _ in runs],
+                    "wall_ms": round(st["wall_ms"], 1),
                     "link_GBps": round((st["bytes_h2d"] + st["bytes_d2h"]) / el / 1e9, 2),
                     "e_total_pooled": e_tot, "e_total_worst_box": e_tot_w,
                     "e_arith_pooled": e_ar, "e_arith_worst_box": e_ar_w,
