@@ -116,6 +116,9 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of one run: the workload under every chunk count x TB depth "
                          "of --sweep-chunks / --sweep-depths, one JSON line each")
+    ap.add_argument("--link-sweep", action="store_true",
+                    help="print one JSON line per copy pattern of the host-link probe (bytes per "
+                         "direction x copies queued) and exit")
     ap.add_argument("--sweep-chunks", default="4,8")
     ap.add_argument("--sweep-depths", default="40,80,160,320,640")
     return ap.parse_args()
@@ -621,6 +624,13 @@ def main():
     w = weights_for(wl, offs)
     if args.kernel_rates:
         return kernel_rates(args, wl, offs, w)
+    if args.link_sweep:
+        for nbytes, pieces in ((1 << 30, 1), (1 << 30, 2), (4 << 30, 8), (4 << 30, 16), (4 << 30, 32),
+                               (8 << 30, 16)):
+            line = {"MiB_per_direction": nbytes >> 20, "copies": pieces}
+            line.update(link_probe(nbytes, pieces))
+            print(json.dumps(line), flush=True)
+        return
     if storage != "f64":
         w = workloads.fp32_rounded(w)
     if wl.extra.get("ckpt_every"):
